@@ -1,0 +1,620 @@
+"""Plain FP64 CPU oracle for the scale-invariant binary MERA hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call this
+module: it exists so that tests, the smoke check and the CPU-baseline leg of the
+benchmark can compare the HIP path against an independent, obviously correct
+implementation.  It shares no code with the HIP path; it takes its inputs from
+``paper_1906_12030_amd.inputs`` (seeded random numbers only).
+
+Everything here is numpy float64.  Superoperators and environments are written
+as their plain definition: the whole causal-cone network of eleven tensors
+(five ket, five bra, plus the density or operator) handed to one ``einsum``,
+one call per placement and per environment contribution.  The contraction
+order is the einsum path's, not the GPU schedule's.
+
+Paper references (Ganahl et al., "TensorNetwork on TensorFlow: Entanglement
+Renormalization for quantum critical lattice models"):
+  * isometric / unitary constraints: Sec. II.A, Eqs. (iso) and (unitarity);
+  * Ising Hamiltonian: Sec. II, Eq. (ham); three-site regrouping: Sec. II.B;
+  * ascending / descending superoperators: Sec. II.B, Fig. 4(a,b);
+  * fixed-point density by iteration, descent, energy: Sec. II.B;
+  * environments (6 contributions for w, 4 for u): Sec. II.C, Fig. 4(c,d),
+    appendix figure A1;
+  * SVD update: Sec. II.C, Fig. 5;  sweep order: Sec. II.C;
+  * scaling dimensions from eigenvalues 2^-Delta of the scale-invariant
+    ascending superoperator: Sec. II.B and Sec. III.A.
+
+Readings of the paper where its figures are missing (all figures of the text
+are absent):
+  * leg order u[a,b,c,d], w[a,b,c]: lower legs first, as in Eqs. (iso),
+    (unitarity) which sum over the first two legs;
+  * geometry: in a layer, coarse site k owns an isometry whose lower legs are
+    intermediate sites (2k, 2k+1); disentanglers act on intermediate pairs
+    (2k+1, 2k+2) and output fine sites (2k+1, 2k+2);
+  * a three-site fine window sits in two inequivalent positions relative to a
+    disentangler pair (L: fine sites 2k-1..2k+1, R: 2k..2k+2), both in the cone
+    of the coarse window (k-1, k, k+1).  Two placements times two disentanglers
+    gives the four u contributions and times three isometries the six w
+    contributions the paper counts.  The averaged superoperators are
+    A = (A_L + A_R)/2 and D = (D_L + D_R)/2;
+  * the transverse field is split evenly over the two bonds of a site:
+    h2 = -X(x)X - (h/2)(Z(x)1 + 1(x)Z);
+  * the Hamiltonian is shifted by c = lambda_max(h3) so that it is negative
+    semidefinite; updates are new = -U V^T from the SVD U S V^T of the
+    environment blocked as (lower legs) x (upper legs);
+  * environments are derivatives of e = tr(h D(rho)) with respect to the ket
+    copies of the tensor only (so <Env_u, u> = 2e and <Env_w, w> = 3e).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+import scipy.sparse
+import scipy.sparse.linalg
+
+# ---------------------------------------------------------------------------
+# Index labels of the causal-cone network (one letter each, for einsum).
+#   fine legs (ket)  f1 f2 f3 f4 ; fine legs (bra) g1 g2 g3 g4
+#   ket internal: a1 b1 b2 a4 (disentangler upper legs), x y (outer legs of
+#   the side isometries, traced between ket and bra), c1 c2 c3 (coarse legs)
+#   bra internal: primed copies a1' b1' b2' a4' c1' c2' c3'
+# ---------------------------------------------------------------------------
+_L = dict(f1="A", f2="B", f3="C", f4="D", g1="E", g2="F", g3="G", g4="H",
+          a1="I", b1="J", b2="K", a4="L", x="M", y="N", c1="O", c2="P", c3="Q",
+          a1p="R", b1p="S", b2p="T", a4p="U", c1p="V", c2p="W", c3p="X")
+
+
+def _s(*names: str) -> str:
+    return "".join(_L[n] for n in names)
+
+
+def _cone(placement: str):
+    """Labels of the eleven-tensor network for placement 'L' or 'R'.
+
+    Returns (ket, bra, coarse, fine) where ket and bra map tensor-copy names to
+    label strings, coarse is the label string of the coarse three-site object
+    (density or ascended operator, ket legs then bra legs), fine that of the
+    fine three-site object.
+    """
+    ket = {
+        "uL": _s("f1", "f2", "a1", "b1"),
+        "uR": _s("f3", "f4", "b2", "a4"),
+        "wL": _s("x", "a1", "c1"),
+        "wC": _s("b1", "b2", "c2"),
+        "wR": _s("a4", "y", "c3"),
+    }
+    coarse = _s("c1", "c2", "c3", "c1p", "c2p", "c3p")
+    if placement == "L":
+        # window (f1, f2, f3); f4 is traced between ket and bra
+        bra = {
+            "uL": _s("g1", "g2", "a1p", "b1p"),
+            "uR": _s("g3", "f4", "b2p", "a4p"),
+        }
+        fine = _s("f1", "f2", "f3", "g1", "g2", "g3")
+    elif placement == "R":
+        # window (f2, f3, f4); f1 is traced between ket and bra
+        bra = {
+            "uL": _s("f1", "g2", "a1p", "b1p"),
+            "uR": _s("g3", "g4", "b2p", "a4p"),
+        }
+        fine = _s("f2", "f3", "f4", "g2", "g3", "g4")
+    else:
+        raise ValueError(placement)
+    bra.update({
+        "wL": _s("x", "a1p", "c1p"),
+        "wC": _s("b1p", "b2p", "c2p"),
+        "wR": _s("a4p", "y", "c3p"),
+    })
+    return ket, bra, coarse, fine
+
+
+def _transpose_label(lbl6: str) -> str:
+    """Swap ket and bra halves of a six-leg label (matrix transpose)."""
+    return lbl6[3:] + lbl6[:3]
+
+
+def _network_operands(u, w, placement, skip_ket=None):
+    ket, bra, coarse, fine = _cone(placement)
+    tens = {"u": u, "w": w}
+    subs, ops = [], []
+    for name, lbl in ket.items():
+        if name == skip_ket:
+            continue
+        subs.append(lbl)
+        ops.append(tens[name[0]])
+    for name, lbl in bra.items():
+        subs.append(lbl)
+        ops.append(tens[name[0]])
+    return subs, ops, coarse, fine
+
+
+_PATH_CACHE: dict = {}
+
+
+def _best_pairwise_order(subs, shapes, out):
+    """Cheapest pairwise contraction order (exact dynamic programme over subsets).
+
+    Only the order of the pairwise products is chosen here; the result is the
+    plain sum over all internal indices whatever the order.  Returns numpy's
+    'einsum_path' list.
+    """
+    key = (tuple(subs), tuple(shapes), out)
+    if key in _PATH_CACHE:
+        return _PATH_CACHE[key]
+    dims = {}
+    for sub, shp in zip(subs, shapes):
+        for ch, n in zip(sub, shp):
+            dims[ch] = n
+    letters = sorted(dims)
+    bit = {ch: 1 << i for i, ch in enumerate(letters)}
+    size = {}
+
+    def lsize(mask):
+        if mask not in size:
+            p = 1.0
+            for ch in letters:
+                if mask & bit[ch]:
+                    p *= dims[ch]
+            size[mask] = p
+        return size[mask]
+
+    n = len(subs)
+    opmask = [sum(bit[ch] for ch in set(sub)) for sub in subs]
+    outmask = sum(bit[ch] for ch in out)
+    full = (1 << n) - 1
+    union = [0] * (1 << n)
+    for s in range(1, 1 << n):
+        low = s & -s
+        union[s] = union[s ^ low] | opmask[low.bit_length() - 1]
+
+    def legs(s):
+        return union[s] & (union[full ^ s] | outmask)
+
+    best = {1 << i: (0.0, None) for i in range(n)}
+    for s in range(1, 1 << n):
+        if s in best:
+            continue
+        bcost, bsplit = None, None
+        sub = (s - 1) & s
+        while sub:
+            other = s ^ sub
+            if sub < other and sub in best and other in best:
+                shared = union[sub] & union[other]
+                if shared or s == full:
+                    c = best[sub][0] + best[other][0] + lsize(legs(sub) | legs(other))
+                    if bcost is None or c < bcost:
+                        bcost, bsplit = c, (sub, other)
+            sub = (sub - 1) & s
+        if bcost is not None:
+            best[s] = (bcost, bsplit)
+    if full not in best:
+        raise ValueError("disconnected network")
+    # flatten the tree into numpy's positional pair list
+    order = []
+
+    def visit(s):
+        split = best[s][1]
+        if split is None:
+            return
+        visit(split[0])
+        visit(split[1])
+        order.append(split)
+
+    visit(full)
+    current = [1 << i for i in range(n)]
+    path = ["einsum_path"]
+    for a, b in order:
+        i, j = current.index(a), current.index(b)
+        path.append((min(i, j), max(i, j)))
+        for k in sorted((i, j), reverse=True):
+            current.pop(k)
+        current.append(a | b)
+    _PATH_CACHE[key] = path
+    return path
+
+
+def _einsum(subs, ops, out):
+    expr = ",".join(subs) + "->" + out
+    path = _best_pairwise_order(subs, [o.shape for o in ops], out)
+    return np.einsum(expr, *ops, optimize=path)
+
+
+# ---------------------------------------------------------------------------
+# Hamiltonian (Sec. II Eq. ham; three-site density Sec. II.B)
+# ---------------------------------------------------------------------------
+PAULI_X = np.array([[0.0, 1.0], [1.0, 0.0]])
+PAULI_Z = np.array([[1.0, 0.0], [0.0, -1.0]])
+ID2 = np.eye(2)
+
+
+def tfim_two_site(hfield: float = 1.0) -> np.ndarray:
+    """Bond term h_{n,n+1} = -X X - (h/2)(Z 1 + 1 Z) as a 4x4 matrix (field split evenly)."""
+    return -np.kron(PAULI_X, PAULI_X) - 0.5 * hfield * (np.kron(PAULI_Z, ID2) + np.kron(ID2, PAULI_Z))
+
+
+def tfim_three_site(hfield: float = 1.0) -> np.ndarray:
+    """h3 = (h2 (x) 1 + 1 (x) h2) / 2 as an 8x8 matrix (Sec. II.B)."""
+    h2 = tfim_two_site(hfield)
+    return 0.5 * (np.kron(h2, ID2) + np.kron(ID2, h2))
+
+
+def shifted_hamiltonian(hfield: float = 1.0):
+    """(h3 - c 1) reshaped to [i1,i2,i3,j1,j2,j3], and the shift c = lambda_max(h3)."""
+    h3 = tfim_three_site(hfield)
+    c = float(np.linalg.eigvalsh(h3)[-1])
+    return (h3 - c * np.eye(8)).reshape((2,) * 6), c
+
+
+# ---------------------------------------------------------------------------
+# Superoperators (Sec. II.B, Fig. 4a,b)
+# ---------------------------------------------------------------------------
+def descend_placement(u, w, rho, placement):
+    """D_P(rho): fine three-site density of window P from the coarse density rho."""
+    subs, ops, coarse, fine = _network_operands(u, w, placement)
+    return _einsum(subs + [coarse], ops + [rho], fine)
+
+
+def ascend_placement(u, w, op, placement):
+    """A_P(op): coarse three-site operator from the fine operator op on window P."""
+    subs, ops, coarse, fine = _network_operands(u, w, placement)
+    return _einsum(subs + [fine], ops + [op], coarse)
+
+
+def descend(u, w, rho):
+    """Averaged descending superoperator D = (D_L + D_R) / 2."""
+    return 0.5 * (descend_placement(u, w, rho, "L") + descend_placement(u, w, rho, "R"))
+
+
+def ascend(u, w, op):
+    """Averaged ascending superoperator A = (A_L + A_R) / 2."""
+    return 0.5 * (ascend_placement(u, w, op, "L") + ascend_placement(u, w, op, "R"))
+
+
+def apply_placement(fn, u, w, x, placement):
+    """placement in {'L','R','AVG'} for fn in {descend_placement, ascend_placement}."""
+    if placement == "AVG":
+        return 0.5 * (fn(u, w, x, "L") + fn(u, w, x, "R"))
+    return fn(u, w, x, placement)
+
+
+# ---------------------------------------------------------------------------
+# Energy and environments (Sec. II.B; Sec. II.C, Fig. 4c,d and Fig. A1)
+# ---------------------------------------------------------------------------
+def trace_product(h, rho):
+    """tr(h rho) = sum_ij h_ij rho_ji for (n x n) matrices given in any shape."""
+    n = int(round(np.sqrt(h.size)))
+    return float(np.sum(h.reshape(n, n) * rho.reshape(n, n).T))
+
+
+def energy_placement(u, w, h, rho, placement):
+    """e_P = tr(h D_P(rho)) contracted as one network (h enters with bra legs first)."""
+    subs, ops, coarse, fine = _network_operands(u, w, placement)
+    return float(_einsum(subs + [coarse, _transpose_label(fine)], ops + [rho, h], ""))
+
+
+def env_contribution(u, w, h, rho, placement, copy):
+    """Derivative of tr(h D_P(rho)) with respect to one ket copy (uL, uR, wL, wC, wR)."""
+    ket, _, _, _ = _cone(placement)
+    subs, ops, coarse, fine = _network_operands(u, w, placement, skip_ket=copy)
+    return _einsum(subs + [coarse, _transpose_label(fine)], ops + [rho, h], ket[copy])
+
+
+def env_u(u, w, h, rho, placement="AVG"):
+    """Environment of u: sum of the contributions of both ket disentanglers.
+
+    With placement AVG this is the paper's four-contribution sum (two placements x
+    two disentanglers) with the 1/2 of the averaged superoperator.
+    """
+    places = ("L", "R") if placement == "AVG" else (placement,)
+    scale = 0.5 if placement == "AVG" else 1.0
+    env = np.zeros_like(u)
+    for p in places:
+        for copy in ("uL", "uR"):
+            env += env_contribution(u, w, h, rho, p, copy)
+    return scale * env
+
+
+def env_w(u, w, h, rho, placement="AVG"):
+    """Environment of w: six contributions (two placements x three ket isometries) for AVG."""
+    places = ("L", "R") if placement == "AVG" else (placement,)
+    scale = 0.5 if placement == "AVG" else 1.0
+    env = np.zeros_like(w)
+    for p in places:
+        for copy in ("wL", "wC", "wR"):
+            env += env_contribution(u, w, h, rho, p, copy)
+    return scale * env
+
+
+# ---------------------------------------------------------------------------
+# SVD update (Sec. II.C, Fig. 5)
+# ---------------------------------------------------------------------------
+def polar_update_matrix(y: np.ndarray):
+    """new = -U V^T for y = U S V^T (rows >= cols); also returns the singular values."""
+    uu, s, vt = np.linalg.svd(y, full_matrices=False)
+    return -(uu @ vt), s
+
+
+def update_u(env):
+    d = env.shape[0]
+    new, _ = polar_update_matrix(env.reshape(d * d, d * d))
+    return new.reshape(env.shape)
+
+
+def update_w(env):
+    din, _, dout = env.shape
+    new, _ = polar_update_matrix(env.reshape(din * din, dout))
+    return new.reshape(env.shape)
+
+
+# ---------------------------------------------------------------------------
+# Fixed point of the scale-invariant descending superoperator (Sec. II.B)
+# ---------------------------------------------------------------------------
+def identity_density(d):
+    n = d ** 3
+    return (np.eye(n) / n).reshape((d,) * 6)
+
+
+def power_iteration_step(u, w, rho):
+    """rho <- D(rho), then symmetrised and normalised to unit trace."""
+    d = rho.shape[0]
+    n = d ** 3
+    r = descend(u, w, rho).reshape(n, n)
+    r = 0.5 * (r + r.T)
+    r = r / np.trace(r)
+    return r.reshape(rho.shape)
+
+
+def fixed_point_rho(u, w, rho0, iters):
+    rho = rho0
+    for _ in range(iters):
+        rho = power_iteration_step(u, w, rho)
+    return rho
+
+
+def fixed_point_residual(u, w, rho):
+    """||D(rho) - rho||_F / ||rho||_F."""
+    r = descend(u, w, rho)
+    return float(np.linalg.norm(r - rho) / np.linalg.norm(rho))
+
+
+# ---------------------------------------------------------------------------
+# Whole state: ascend / descend chains, energy, sweep (Sec. II.B, II.C)
+# ---------------------------------------------------------------------------
+class MeraState:
+    """Transitional layers [(u_t, w_t)], scale-invariant (u_s, w_s), fixed point rho*."""
+
+    def __init__(self, layers, si, rho_star=None):
+        self.layers = [(np.array(u, dtype=np.float64), np.array(w, dtype=np.float64)) for u, w in layers]
+        self.si = (np.array(si[0], dtype=np.float64), np.array(si[1], dtype=np.float64))
+        d = self.si[0].shape[0]
+        self.rho_star = identity_density(d) if rho_star is None else np.array(rho_star, dtype=np.float64)
+
+    def copy(self):
+        return MeraState(self.layers, self.si, self.rho_star.copy())
+
+
+def ascend_chain(state: MeraState, h1):
+    """[h_1, h_2, ..., h_{T+1}] with h_{t+1} = A_t(h_t)."""
+    hs = [h1]
+    for u, w in state.layers:
+        hs.append(ascend(u, w, hs[-1]))
+    return hs
+
+
+def descend_chain(state: MeraState, rho_top):
+    """[rho_1, ..., rho_{T+1}] with rho_{T+1} = rho_top and rho_t = D_t(rho_{t+1})."""
+    rhos = [rho_top]
+    for u, w in reversed(state.layers):
+        rhos.append(descend(u, w, rhos[-1]))
+    return rhos[::-1]
+
+
+def energy(state: MeraState, h1, shift=0.0):
+    """Energy per site tr(h_1 rho_1) + shift, rho_1 descended from rho*."""
+    rho1 = descend_chain(state, state.rho_star)[0]
+    return trace_product(h1, rho1) + shift
+
+
+def si_environments_h(state: MeraState, h_top, si_levels=1):
+    """Operators seen by the first si_levels scale-invariant layers."""
+    u, w = state.si
+    hs = [h_top]
+    for _ in range(si_levels - 1):
+        hs.append(ascend(u, w, hs[-1]))
+    return hs
+
+
+def sweep(state: MeraState, h1, shift=0.0, iters=30, si_levels=1):
+    """One optimisation sweep; returns the energy per site after it.
+
+    Order: ascend h with the current tensors; update the scale-invariant layer
+    (u then w) against rho*; recompute rho* by ``iters`` power iterations
+    started from the previous rho*; then update transitional layers top-down
+    (u then w), descending rho with the updated tensors as we go.
+    """
+    hs = ascend_chain(state, h1)
+    # scale-invariant layer
+    u, w = state.si
+    h_si = si_environments_h(state, hs[-1], si_levels)
+    eu = sum(env_u(u, w, hk, state.rho_star) for hk in h_si)
+    u = update_u(eu)
+    ew = sum(env_w(u, w, hk, state.rho_star) for hk in h_si)
+    w = update_w(ew)
+    state.si = (u, w)
+    state.rho_star = fixed_point_rho(u, w, state.rho_star, iters)
+    # transitional layers, top-down
+    rho = state.rho_star
+    for t in reversed(range(len(state.layers))):
+        u, w = state.layers[t]
+        u = update_u(env_u(u, w, hs[t], rho))
+        w = update_w(env_w(u, w, hs[t], rho))
+        state.layers[t] = (u, w)
+        rho = descend(u, w, rho)
+    return trace_product(h1, rho) + shift
+
+
+def initial_fixed_point(state: MeraState, iters=30):
+    u, w = state.si
+    state.rho_star = fixed_point_rho(u, w, state.rho_star, iters)
+
+
+# ---------------------------------------------------------------------------
+# Scaling dimensions (Sec. II.B, Sec. III.A)
+# ---------------------------------------------------------------------------
+def scaling_dimensions(u, w, k=12):
+    """Delta = -log2 |lambda| for the k eigenvalues of largest modulus of A (scale-invariant)."""
+    d = u.shape[0]
+    n = d ** 6
+
+    def mv(x):
+        return ascend(u, w, x.reshape((d,) * 6)).reshape(-1)
+
+    op = scipy.sparse.linalg.LinearOperator((n, n), matvec=mv, dtype=np.float64)
+    if n <= 2000:
+        m = np.column_stack([mv(e) for e in np.eye(n)])
+        lam = scipy.linalg.eigvals(m)
+    else:
+        lam = scipy.sparse.linalg.eigs(op, k=k, which="LM", return_eigenvectors=False, tol=1e-12)
+    lam = lam[np.argsort(-np.abs(lam))][:k]
+    return -np.log2(np.abs(lam)), lam
+
+
+# ---------------------------------------------------------------------------
+# Finite periodic binary MERA on 16 sites (Fig. 1b) and exact diagonalisation
+# ---------------------------------------------------------------------------
+def apply_layer_to_state(psi, n_coarse, u, w):
+    """Map a state on n_coarse periodic sites to 2*n_coarse sites through one layer.
+
+    psi has shape (dc,)*n_coarse.  Coarse site k becomes intermediate sites
+    (2k, 2k+1) through w; then u acts on intermediate pairs (2k+1, 2k+2 mod 2n).
+    """
+    din = w.shape[0]
+    t = psi
+    # isometries: replace each coarse leg c by two legs (a, b)
+    for k in range(n_coarse):
+        # the coarse leg k is at axis 2k (the first k legs already doubled)
+        axis = 2 * k
+        t = np.tensordot(t, w, axes=([axis], [2]))  # new legs (a, b) appended at the end
+        t = np.moveaxis(t, [-2, -1], [axis, axis + 1])
+    n_int = 2 * n_coarse
+    # disentanglers on (2k+1, 2k+2 mod n_int): u[a,b,c,d] maps upper (c,d) -> lower (a,b)
+    for k in range(n_coarse):
+        i, j = 2 * k + 1, (2 * k + 2) % n_int
+        t = np.tensordot(t, u, axes=([i, j], [2, 3]))
+        t = np.moveaxis(t, [-2, -1], [i, j])
+    assert t.shape == (din,) * n_int
+    return t
+
+
+def finite_state(layers, top):
+    """State vector of the periodic finite MERA: top state on n_top sites, then layers top-down."""
+    n = top.ndim
+    psi = top
+    for u, w in reversed(layers):
+        psi = apply_layer_to_state(psi, n, u, w)
+        n *= 2
+    return psi
+
+
+def reduced_density_three(psi, n):
+    """Reduced density of sites (n, n+1, n+2) mod N of a real state psi, as [i1 i2 i3 j1 j2 j3]."""
+    nsite = psi.ndim
+    sites = [n % nsite, (n + 1) % nsite, (n + 2) % nsite]
+    rest = [s for s in range(nsite) if s not in sites]
+    t = np.transpose(psi, sites + rest)
+    d = psi.shape[0]
+    m = t.reshape(d ** 3, -1)
+    return (m @ m.T).reshape((d,) * 6)
+
+
+def top_density(top, start):
+    """Reduced density of three consecutive top sites (start, start+1, start+2) mod n_top."""
+    return reduced_density_three(top, start)
+
+
+def fine_window_from_coarse(n):
+    """Window n on the finer level -> (placement, start of the coarse window).
+
+    n = 2k-1 (odd) is the L window of coarse window (k-1, k, k+1); n = 2k (even)
+    is its R window.
+    """
+    if n % 2 == 1:
+        return "L", (n - 1) // 2
+    return "R", n // 2 - 1
+
+
+def tfim_periodic_sparse(nsite, hfield=1.0):
+    """Sparse H = sum_n -X_n X_{n+1} - h Z_n with periodic boundary conditions."""
+    dim = 2 ** nsite
+    idx = np.arange(dim)
+    diag = np.zeros(dim)
+    rows, cols, vals = [], [], []
+    for n in range(nsite):
+        bit = nsite - 1 - n  # site 0 is the most significant bit (C order of psi)
+        zn = 1.0 - 2.0 * ((idx >> bit) & 1)
+        diag += -hfield * zn
+        m = (n + 1) % nsite
+        bitm = nsite - 1 - m
+        flipped = idx ^ (1 << bit) ^ (1 << bitm)
+        rows.append(flipped)
+        cols.append(idx)
+        vals.append(-np.ones(dim))
+    rows.append(idx)
+    cols.append(idx)
+    vals.append(diag)
+    return scipy.sparse.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                   shape=(dim, dim))
+
+
+def ising_ground_energy_closed_form(nsite):
+    """Periodic critical Ising chain: E_0 = -2 / sin(pi / (2N)) (free-fermion solution)."""
+    return -2.0 / np.sin(np.pi / (2 * nsite))
+
+
+# ---------------------------------------------------------------------------
+# Dense-matrix formulation of D (independent of the einsum network)
+# ---------------------------------------------------------------------------
+def descend_dense(u, w, rho):
+    """D_L and D_R from V = (1_x (x) u (x) u (x) 1_y)(w (x) w (x) w) and partial traces.
+
+    V maps three coarse sites to six fine legs (x, f1, f2, f3, f4, y); D_L traces
+    (x, f4, y) out of V rho V^T and D_R traces (x, f1, y).
+    """
+    din = w.shape[0]
+    dout = w.shape[2]
+    wm = w.reshape(din * din, dout)
+    um = u.reshape(din * din, din * din)
+    www = np.kron(np.kron(wm, wm), wm)  # (x a1)(b1 b2)(a4 y) <- (c1 c2 c3)
+    eye = np.eye(din)
+    uu = np.kron(np.kron(np.kron(eye, um), um), eye)  # legs x,(a1 b1),(b2 a4),y -> x,(f1 f2),(f3 f4),y
+    v = uu @ www
+    n = dout ** 3
+    big = v @ rho.reshape(n, n) @ v.T
+    big = big.reshape((din,) * 12)  # x f1 f2 f3 f4 y | x' g1 g2 g3 g4 y'
+    t = big
+    # trace x with x', y with y'
+    t = np.trace(t, axis1=0, axis2=6)            # f1 f2 f3 f4 y g1 g2 g3 g4 y'
+    t = np.trace(t, axis1=4, axis2=9)            # f1 f2 f3 f4 g1 g2 g3 g4
+    dl = np.trace(t, axis1=3, axis2=7)           # f1 f2 f3 g1 g2 g3
+    dr = np.trace(t, axis1=0, axis2=4)           # f2 f3 f4 g2 g3 g4
+    return dl, dr
+
+
+# ---------------------------------------------------------------------------
+# Binary tree (u = identity) descending superoperator, written independently
+# ---------------------------------------------------------------------------
+def descend_tree(w, rho):
+    """Tree-network descent (Fig. 1a geometry) for the L and R windows.
+
+    L window: fine site 1 is the right child of the left isometry, fine sites 2, 3
+    are the children of the centre isometry; the right coarse site is traced.
+    R window: fine sites 1, 2 are the centre's children, site 3 the left child of
+    the right isometry; the left coarse site is traced.
+    """
+    d = rho.shape[0]
+    r = rho
+    rho12 = np.einsum("abcdec->abde", r)   # trace coarse site 3
+    rho23 = np.einsum("abcaef->bcef", r)   # trace coarse site 1
+    dl = np.einsum("xpi,qrj,ijkl,xsk,tul->pqrstu", w, w, rho12, w, w, optimize=True)
+    dr = np.einsum("pqi,rxj,ijkl,stk,uxl->pqrstu", w, w, rho23, w, w, optimize=True)
+    return dl, dr

@@ -1,0 +1,356 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these tests re-types an oracle formula: each compares the oracle with
+an independent construction (brute-force state vectors, Kronecker-product
+matrices, a tree network, exact diagonalisation, closed forms) or with an
+invariant that a dropped term, wrong sign, wrong index or transposed operand
+would break.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg
+
+from oracle import mera_oracle as O
+from paper_1906_12030_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _consts():
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as f:
+        return json.load(f)
+
+
+def _iso_err_u(u):
+    d = u.shape[0]
+    m = u.reshape(d * d, d * d)
+    return np.abs(m.T @ m - np.eye(d * d)).max()
+
+
+def _iso_err_w(w):
+    din, _, dout = w.shape
+    m = w.reshape(din * din, dout)
+    return np.abs(m.T @ m - np.eye(dout)).max()
+
+
+# ----------------------------------------------------------------------------
+# Hamiltonian: Eq. (ham) and the three-site regrouping (Sec. II.B)
+# ----------------------------------------------------------------------------
+def test_three_site_terms_sum_to_periodic_chain():
+    """sum_n h3_{n,n+1,n+2} equals the Pauli-string H = -sum XX - sum Z on a ring."""
+    n = 8
+    h3 = O.tfim_three_site(1.0)
+    dim = 2 ** n
+    total = np.zeros((dim, dim))
+    for s in range(n):
+        # embed h3 on sites (s, s+1, s+2) mod n by permuting a dense Kronecker product
+        op = np.kron(h3, np.eye(2 ** (n - 3))).reshape((2,) * (2 * n))
+        perm_sites = [(s + k) % n for k in range(n)]
+        inv = np.argsort(perm_sites)
+        op = np.transpose(op, list(inv) + [n + i for i in inv])
+        total += op.reshape(dim, dim)
+    ref = O.tfim_periodic_sparse(n, 1.0).toarray()
+    assert np.abs(total - ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("nsite", [8, 12, 16])
+def test_periodic_chain_ground_energy_closed_form(nsite):
+    """Lanczos ground energy of the periodic critical chain vs -2/sin(pi/2N)."""
+    hsp = O.tfim_periodic_sparse(nsite, 1.0)
+    e0 = scipy.sparse.linalg.eigsh(hsp, k=1, which="SA", tol=1e-13)[0][0]
+    assert abs(e0 - O.ising_ground_energy_closed_form(nsite)) < 1e-9 * nsite
+
+
+def test_infinite_chain_limit_is_minus_four_over_pi():
+    """E_0(N)/N approaches the paper's e_exact = -4/pi (Sec. III.A) as N grows."""
+    c = _consts()["exact_energy_density"]["value"]
+    assert abs(c + 4 / np.pi) < 1e-15
+    e = [O.ising_ground_energy_closed_form(n) / n for n in (64, 256, 1024)]
+    errs = [abs(x - c) for x in e]
+    assert errs[0] > errs[1] > errs[2]
+    # finite-size correction ~ pi c_CFT /(6 N^2) with c = 1/2 (1/N^2 scaling)
+    assert errs[2] < 2e-6 and abs(errs[1] / errs[2] - 16) < 0.1
+
+
+def test_shift_makes_hamiltonian_negative_semidefinite():
+    h, c = O.shifted_hamiltonian()
+    ev = np.linalg.eigvalsh(h.reshape(8, 8))
+    assert abs(ev[-1]) < 1e-14 and ev[0] < 0
+    # the spectrum of h3 with an evenly split field is symmetric about zero
+    ev3 = np.linalg.eigvalsh(O.tfim_three_site())
+    assert np.allclose(np.sort(ev3), np.sort(-ev3), atol=1e-14)
+    assert abs(c - ev3[-1]) < 1e-15
+
+
+# ----------------------------------------------------------------------------
+# Constraints (Eqs. iso, unitarity) and the SVD update (Fig. 5)
+# ----------------------------------------------------------------------------
+def test_initial_tensors_obey_constraints():
+    layers, si = I.init_mera(8, 3, 0)
+    for u, w in layers + [si]:
+        assert _iso_err_u(u) < 1e-13
+        assert _iso_err_w(w) < 1e-13
+
+
+@pytest.mark.parametrize("rows,cols", [(16, 16), (64, 8), (81, 9), (9, 3)])
+def test_polar_update_properties(rows, cols):
+    """new = -U V^T: isometric, Y^T new = -P with P symmetric PSD, <Y,new> = -||Y||_*."""
+    rng = np.random.default_rng(rows * 100 + cols)
+    y = rng.standard_normal((rows, cols))
+    new, s = O.polar_update_matrix(y)
+    assert np.abs(new.T @ new - np.eye(cols)).max() < 1e-13
+    p = -(y.T @ new)
+    assert np.abs(p - p.T).max() < 1e-12
+    assert np.linalg.eigvalsh(0.5 * (p + p.T)).min() > -1e-12
+    nuc = np.linalg.norm(y, "nuc")
+    assert abs(np.sum(y * new) + nuc) < 1e-11 * nuc
+    # -new minimises <Y, X> over isometries X: compare with random isometries
+    for k in range(20):
+        q = I.random_isometry_matrix(rng, rows, cols)
+        assert np.sum(y * q) >= np.sum(y * new) - 1e-12
+
+
+def test_updates_keep_constraints():
+    rng = np.random.default_rng(3)
+    u = O.update_u(rng.standard_normal((3, 3, 3, 3)))
+    w = O.update_w(rng.standard_normal((3, 3, 2)))
+    assert _iso_err_u(u) < 1e-13 and _iso_err_w(w) < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# Superoperators: dense-matrix formulation, duality, unitality, positivity
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("din,dout", [(2, 2), (2, 4), (3, 3), (3, 2), (4, 4)])
+def test_descend_matches_kronecker_formulation(din, dout):
+    rng = np.random.default_rng(10 * din + dout)
+    u, w = I.random_layer(rng, din, dout)
+    rho = I.random_density(rng, dout)
+    dl, dr = O.descend_dense(u, w, rho)
+    assert np.abs(O.descend_placement(u, w, rho, "L") - dl).max() < 1e-13
+    assert np.abs(O.descend_placement(u, w, rho, "R") - dr).max() < 1e-13
+
+
+@pytest.mark.parametrize("din,dout", [(2, 4), (3, 3), (4, 3)])
+@pytest.mark.parametrize("placement", ["L", "R"])
+def test_ascend_is_adjoint_of_descend(din, dout, placement):
+    """tr(A_P(o) rho) = tr(o D_P(rho)) for general (non-symmetric) o and rho."""
+    rng = np.random.default_rng(7 * din + dout)
+    u, w = I.random_layer(rng, din, dout)
+    o = rng.standard_normal((din,) * 6)
+    rho = rng.standard_normal((dout,) * 6)
+    lhs = O.trace_product(O.ascend_placement(u, w, o, placement), rho)
+    rhs = O.trace_product(o, O.descend_placement(u, w, rho, placement))
+    assert abs(lhs - rhs) < 1e-12 * (1 + abs(lhs))
+
+
+@pytest.mark.parametrize("placement", ["L", "R"])
+def test_unital_trace_preserving_positive(placement):
+    rng = np.random.default_rng(5)
+    din, dout = 3, 3
+    u, w = I.random_layer(rng, din, dout)
+    eye_in = np.eye(din ** 3).reshape((din,) * 6)
+    a = O.ascend_placement(u, w, eye_in, placement).reshape(dout ** 3, dout ** 3)
+    assert np.abs(a - np.eye(dout ** 3)).max() < 1e-13
+    rho = I.random_density(rng, dout, rank=3)
+    d = O.descend_placement(u, w, rho, placement).reshape(din ** 3, din ** 3)
+    assert abs(np.trace(d) - 1.0) < 1e-13
+    assert np.linalg.eigvalsh(0.5 * (d + d.T)).min() > -1e-13
+
+
+def test_tree_special_case():
+    """u = identity turns the binary MERA into the binary tree of Fig. 1a."""
+    rng = np.random.default_rng(11)
+    for din, dout in [(2, 3), (3, 3)]:
+        _, w = I.random_layer(rng, din, dout)
+        eye = np.eye(din * din).reshape(din, din, din, din)
+        rho = I.random_density(rng, dout)
+        tl, tr = O.descend_tree(w, rho)
+        assert np.abs(O.descend_placement(eye, w, rho, "L") - tl).max() < 1e-13
+        assert np.abs(O.descend_placement(eye, w, rho, "R") - tr).max() < 1e-13
+
+
+def test_reflection_maps_left_placement_to_right():
+    """For reflection-symmetric tensors D_R(rho) = R D_L(R rho R) R (site order reversed)."""
+    rng = np.random.default_rng(2)
+    u, w = I.reflection_symmetric_layer(rng, 3)
+    rho = I.random_density(rng, 3)
+
+    def rev(x):
+        return np.transpose(x, (2, 1, 0, 5, 4, 3))
+
+    assert np.abs(O.descend_placement(u, w, rho, "R") - rev(O.descend_placement(u, w, rev(rho), "L"))).max() < 1e-13
+    # generic tensors break the symmetry (the test would notice a swapped placement)
+    u2, w2 = I.random_layer(rng, 3, 3)
+    assert np.abs(O.descend_placement(u2, w2, rho, "R") - rev(O.descend_placement(u2, w2, rev(rho), "L"))).max() > 1e-3
+
+
+def test_energy_is_layer_independent_along_chain():
+    """tr(h_t rho_t) is the same at every level of one fixed MERA."""
+    layers, si = I.init_mera(4, 2, 1)
+    st = O.MeraState(layers, si)
+    O.initial_fixed_point(st, 10)
+    h, _ = O.shifted_hamiltonian()
+    hs = O.ascend_chain(st, h)
+    rhos = O.descend_chain(st, st.rho_star)
+    vals = [O.trace_product(hh, rr) for hh, rr in zip(hs, rhos)]
+    assert np.ptp(vals) < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# 16-site finite binary MERA: brute-force state vector (Fig. 1b)
+# ----------------------------------------------------------------------------
+def _finite_network(d2, d3, seed):
+    rng = np.random.default_rng(seed)
+    l1 = I.random_layer(rng, 2, d2)
+    l2 = I.random_layer(rng, d2, d3)
+    top = rng.standard_normal((d3,) * 4)
+    top /= np.linalg.norm(top)
+    return [l1, l2], top
+
+
+def _cone_densities(layers, top):
+    """Fine-level window densities obtained by descending through the causal cone."""
+    (u1, w1), (u2, w2) = layers
+    rho_top = [O.top_density(top, s) for s in range(4)]
+    rho1 = []
+    for n in range(8):
+        p, s = O.fine_window_from_coarse(n)
+        rho1.append(O.descend_placement(u2, w2, rho_top[s % 4], p))
+    rho0 = []
+    for n in range(16):
+        p, s = O.fine_window_from_coarse(n)
+        rho0.append(O.descend_placement(u1, w1, rho1[s % 8], p))
+    return rho_top, rho1, rho0
+
+
+@pytest.mark.parametrize("d2,d3,seed", [(3, 3, 0), (4, 3, 1)])
+def test_sixteen_site_brute_force(d2, d3, seed):
+    layers, top = _finite_network(d2, d3, seed)
+    psi = O.finite_state(layers, top)
+    assert psi.shape == (2,) * 16
+    assert abs(np.linalg.norm(psi) - 1.0) < 1e-13
+    # level-1 state (8 sites) for the intermediate check
+    psi1 = O.apply_layer_to_state(top, 4, *layers[1])
+    _, rho1, rho0 = _cone_densities(layers, top)
+    for n in range(8):
+        assert np.abs(rho1[n] - O.reduced_density_three(psi1, n)).max() < 1e-13
+    for n in range(16):
+        assert np.abs(rho0[n] - O.reduced_density_three(psi, n)).max() < 1e-13
+    # energy: <psi|H|psi> = sum_n tr(h3 rho_n), and it is above the exact ground energy
+    hsp = O.tfim_periodic_sparse(16, 1.0)
+    v = psi.reshape(-1)
+    e_brute = float(v @ (hsp @ v))
+    h3 = O.tfim_three_site().reshape((2,) * 6)
+    e_cone = sum(O.trace_product(h3, r) for r in rho0)
+    assert abs(e_brute - e_cone) < 1e-12 * 16
+    assert e_brute >= O.ising_ground_energy_closed_form(16) - 1e-10
+
+
+def _tangent(x, delta):
+    m = x.reshape(-1, x.shape[-1] if x.ndim == 3 else x.shape[0] * x.shape[1])
+    dm = delta.reshape(m.shape)
+    s = m.T @ dm
+    return (dm - m @ (0.5 * (s + s.T))).reshape(x.shape)
+
+
+def test_sixteen_site_gradients_are_environments():
+    """Central FD of <psi|H|psi>/16 along tangent directions vs 2 <Env, Delta>."""
+    layers, top = _finite_network(3, 3, 4)
+    hsp = O.tfim_periodic_sparse(16, 1.0)
+    h3 = O.tfim_three_site().reshape((2,) * 6)
+
+    def e_total(lay):
+        v = O.finite_state(lay, top).reshape(-1)
+        return float(v @ (hsp @ v)) / 16
+
+    rho_top, rho1, _ = _cone_densities(layers, top)
+    rho1_bar = sum(rho1) / 8
+    rho2_bar = sum(rho_top) / 4
+    (u1, w1), (u2, w2) = layers
+    h2 = O.ascend(u1, w1, h3)
+    envs = {
+        (0, "u"): O.env_u(u1, w1, h3, rho1_bar), (0, "w"): O.env_w(u1, w1, h3, rho1_bar),
+        (1, "u"): O.env_u(u2, w2, h2, rho2_bar), (1, "w"): O.env_w(u2, w2, h2, rho2_bar),
+    }
+    rng = np.random.default_rng(9)
+    eps = 1e-5
+    for (lay, kind), env in envs.items():
+        x = layers[lay][0 if kind == "u" else 1]
+        delta = _tangent(x, rng.standard_normal(x.shape))
+
+        def shifted(sign):
+            lay_list = [list(t) for t in layers]
+            lay_list[lay][0 if kind == "u" else 1] = x + sign * eps * delta
+            return [tuple(t) for t in lay_list]
+
+        fd = (e_total(shifted(+1)) - e_total(shifted(-1))) / (2 * eps)
+        an = 2 * np.sum(env * delta)
+        assert abs(fd - an) < 1e-7 * (1 + abs(an)), (lay, kind, fd, an)
+
+
+# ----------------------------------------------------------------------------
+# Environments: Euler identities and finite differences (Fig. 4c,d; Fig. A1)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("din,dout", [(2, 4), (3, 3)])
+def test_environment_euler_identities(din, dout):
+    rng = np.random.default_rng(din + 10 * dout)
+    u, w = I.random_layer(rng, din, dout)
+    h = I.random_symmetric(rng, din)
+    rho = I.random_density(rng, dout)
+    e = O.trace_product(h, O.descend(u, w, rho))
+    for p in ("L", "R"):
+        ep = O.energy_placement(u, w, h, rho, p)
+        assert abs(np.sum(O.env_u(u, w, h, rho, p) * u) - 2 * ep) < 1e-12 * (1 + abs(ep))
+        assert abs(np.sum(O.env_w(u, w, h, rho, p) * w) - 3 * ep) < 1e-12 * (1 + abs(ep))
+    assert abs(np.sum(O.env_u(u, w, h, rho) * u) - 2 * e) < 1e-12 * (1 + abs(e))
+    assert abs(np.sum(O.env_w(u, w, h, rho) * w) - 3 * e) < 1e-12 * (1 + abs(e))
+
+
+@pytest.mark.parametrize("din,dout", [(2, 4), (3, 2)])
+def test_environment_finite_differences(din, dout):
+    """e(u) = tr(h D(rho)) is a polynomial: its gradient over all copies is 2 Env."""
+    rng = np.random.default_rng(33 + din)
+    u, w = I.random_layer(rng, din, dout)
+    h = I.random_symmetric(rng, din)
+    rho = I.random_density(rng, dout)
+    eu = O.env_u(u, w, h, rho)
+    ew = O.env_w(u, w, h, rho)
+    eps = 1e-5
+    for _ in range(4):
+        du = rng.standard_normal(u.shape)
+        dw = rng.standard_normal(w.shape)
+        fu = (O.trace_product(h, O.descend(u + eps * du, w, rho)) - O.trace_product(h, O.descend(u - eps * du, w, rho))) / (2 * eps)
+        fw = (O.trace_product(h, O.descend(u, w + eps * dw, rho)) - O.trace_product(h, O.descend(u, w - eps * dw, rho))) / (2 * eps)
+        assert abs(fu - 2 * np.sum(eu * du)) < 1e-7 * (1 + abs(fu))
+        assert abs(fw - 2 * np.sum(ew * dw)) < 1e-7 * (1 + abs(fw))
+
+
+# ----------------------------------------------------------------------------
+# Fixed point (Sec. II.B) vs the dense dominant eigenvector
+# ----------------------------------------------------------------------------
+def test_fixed_point_is_dominant_eigenvector():
+    rng = np.random.default_rng(8)
+    d = 2
+    u, w = I.random_layer(rng, d, d)
+    n = d ** 6
+    mat = np.column_stack([O.descend(u, w, e.reshape((d,) * 6)).reshape(-1) for e in np.eye(n)])
+    lam, vec = np.linalg.eig(mat)
+    k = np.argmax(np.abs(lam))
+    assert abs(lam[k] - 1.0) < 1e-12
+    v = np.real(vec[:, k]).reshape(d ** 3, d ** 3)
+    v = v / np.trace(v)
+    rho = O.fixed_point_rho(u, w, O.identity_density(d), 300)
+    assert np.abs(rho.reshape(d ** 3, d ** 3) - v).max() < 1e-12
+    assert O.fixed_point_residual(u, w, rho) < 1e-12
+    assert np.linalg.eigvalsh(rho.reshape(d ** 3, d ** 3)).min() > -1e-13
+
+
+def test_scaling_dimension_of_identity_is_zero():
+    """A is unital, so lambda = 1 (Delta = 0) is always in the spectrum (Sec. III.A)."""
+    rng = np.random.default_rng(4)
+    u, w = I.random_layer(rng, 2, 2)
+    dims, lam = O.scaling_dimensions(u, w, k=4)
+    assert abs(dims[0]) < 1e-12 and abs(lam[0] - 1) < 1e-12
