@@ -1,0 +1,169 @@
+/*
+ * mera.h - C ABI of the MI355X scale-invariant binary MERA hot path.
+ *
+ * The operations follow Ganahl, Milsted, Leichenauer, Hidary and Vidal,
+ * "TensorNetwork on TensorFlow: Entanglement Renormalization for quantum
+ * critical lattice models" (arXiv:1906.12030):
+ *   ascending / descending superoperators  - Sec. II.B, Fig. 4(a,b)
+ *   environments of w (6 terms) and u (4)   - Sec. II.C, Fig. 4(c,d), Fig. A1
+ *   SVD (polar) update                      - Sec. II.C, Fig. 5
+ *   fixed-point density of the scale-invariant layer by iteration - Sec. II.B
+ *   energy tr(h rho)                        - Sec. II.B
+ *
+ * Conventions shared by every call
+ *   - Every pointer whose name ends in _d is a DEVICE pointer (HIP global
+ *     memory) owned by the caller.  The library never allocates, frees or keeps
+ *     caller memory; the caller keeps buffers alive until the stream has
+ *     finished the work.
+ *   - All tensors are float64, dense, row-major (C order), no padding.
+ *       u[a,b,c,d]  disentangler, din^4:  (a,b) lower (finer) legs, (c,d) upper;
+ *                   sum_ab u[ab,cd] u[ab,c'd'] = delta (Eq. unitarity).
+ *       w[a,b,c]    isometry, din*din*dout: (a,b) lower legs, c upper leg;
+ *                   sum_ab w[ab,c] w[ab,c'] = delta (Eq. iso).
+ *       three-site operators / densities: (d^3 x d^3) matrices stored as
+ *                   [i1,i2,i3, j1,j2,j3] (rows = ket legs, columns = bra legs).
+ *   - Geometry: coarse site k owns an isometry on intermediate sites (2k,2k+1);
+ *     disentanglers act on intermediate pairs (2k+1,2k+2).  A fine three-site
+ *     window sits in two positions under the coarse window (k-1,k,k+1):
+ *     LEFT = fine sites 2k-1..2k+1, RIGHT = 2k..2k+2.  AVG = (LEFT+RIGHT)/2,
+ *     the translation-averaged superoperator.
+ *   - `precision` selects the internal contraction arithmetic only; inputs and
+ *     outputs stay float64.  MERA_FP64: FP64 MFMA.  MERA_FP32: operands rounded
+ *     to FP32, FP32 MFMA.  MERA_BF16X3: operands rounded to FP32 and split into
+ *     bf16 hi+lo pairs, products hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32
+ *     accumulation.
+ *   - Work is enqueued on `hip_stream` (a hipStream_t; NULL = default stream)
+ *     and is asynchronous unless a call says otherwise.
+ *   - `ws_d`/`ws_bytes`: caller-provided device workspace of at least
+ *     mera_workspace_bytes(...) bytes, 256-byte aligned.  It must not overlap
+ *     any input or output.  Inputs and outputs must not overlap each other.
+ *   - Errors: the return value is a mera_status.  All argument and shape checks
+ *     happen on the host before any HIP call, so an invalid call enqueues
+ *     nothing and leaves outputs untouched.  MERA_EDEVICE reports a failed HIP
+ *     call (its text via mera_last_error()).  Nothing throws across the ABI.
+ *   - Thread safety: calls keep no state between them (apart from the
+ *     thread-local last-error text) and may be made from several threads on
+ *     different streams with different workspaces.
+ */
+#ifndef MERA_H
+#define MERA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MERA_OK = 0,
+  MERA_EINVAL = 1,      /* null pointer, enum out of range, bad count */
+  MERA_ESHAPE = 2,      /* inconsistent dimensions (e.g. dout > din^2, rows < cols) */
+  MERA_EWORKSPACE = 3,  /* workspace smaller than mera_workspace_bytes() */
+  MERA_EDEVICE = 4,     /* a HIP call failed */
+  MERA_ENUMERIC = 5,    /* non-finite data, or a polar iteration that did not converge */
+  MERA_ENOTCONV = 6     /* reserved */
+} mera_status;
+
+typedef enum { MERA_LEFT = 0, MERA_RIGHT = 1, MERA_AVG = 2 } mera_placement;
+typedef enum { MERA_FP64 = 0, MERA_FP32 = 1, MERA_BF16X3 = 2 } mera_precision;
+
+typedef enum {
+  MERA_OP_ASCEND = 0,
+  MERA_OP_DESCEND = 1,
+  MERA_OP_ENV_U = 2,
+  MERA_OP_ENV_W = 3,
+  MERA_OP_POLAR = 4,        /* din = rows, dout = cols of the blocked environment */
+  MERA_OP_FIXED_POINT = 5,  /* din = dout = d of the scale-invariant layer */
+  MERA_OP_ENERGY = 6
+} mera_op;
+
+/* One MERA layer: disentangler u (din^4) and isometry w (din*din*dout), both
+ * device pointers.  1 <= dout <= din*din. */
+typedef struct {
+  int32_t din;
+  int32_t dout;
+  const double* u_d;
+  const double* w_d;
+} mera_layer;
+
+/* Ascending superoperator (Sec. II.B, Fig. 4a): h_out = A_P(h_in).
+ * h_in_d: din^6 operator on the fine window; h_out_d: dout^6 operator on the
+ * coarse window.  A_P is the adjoint of D_P: tr(A_P(o) rho) = tr(o D_P(rho)). */
+int mera_ascend(const mera_layer* layer, const double* h_in_d, double* h_out_d, int placement,
+                int precision, void* ws_d, size_t ws_bytes, void* hip_stream);
+
+/* Descending superoperator (Sec. II.B, Fig. 4b): rho_out = D_P(rho_in).
+ * rho_in_d: dout^6 coarse density; rho_out_d: din^6 fine density. */
+int mera_descend(const mera_layer* layer, const double* rho_in_d, double* rho_out_d, int placement,
+                 int precision, void* ws_d, size_t ws_bytes, void* hip_stream);
+
+/* Environment of the disentangler (Sec. II.C, Fig. 4d, Fig. A1b):
+ * env_u = d e / d(ket copies of u), e = tr(h D_P(rho)).  With MERA_AVG this is
+ * the sum of the four contributions (two placements x two disentanglers) with
+ * the 1/2 of the averaged superoperator.  h_d: din^6, rho_d: dout^6,
+ * env_u_d: din^4.  Euler: <env_u, u> = 2e. */
+int mera_env_u(const mera_layer* layer, const double* h_d, const double* rho_d, double* env_u_d,
+               int placement, int precision, void* ws_d, size_t ws_bytes, void* hip_stream);
+
+/* Environment of the isometry (Sec. II.C, Fig. 4c, Fig. A1a): the six
+ * contributions (two placements x three isometries) for MERA_AVG.
+ * env_w_d: din*din*dout.  Euler: <env_w, w> = 3e. */
+int mera_env_w(const mera_layer* layer, const double* h_d, const double* rho_d, double* env_w_d,
+               int placement, int precision, void* ws_d, size_t ws_bytes, void* hip_stream);
+
+/* SVD update (Sec. II.C, Fig. 5): out = -U V^T where env = U S V^T is the
+ * environment blocked as a rows x cols matrix (rows = lower legs, cols = upper
+ * legs; rows >= cols), i.e. minus the orthogonal polar factor of env.
+ * FP64 only, computed on the device by a Newton-Schulz polar iteration.
+ * Synchronises `hip_stream` (it reads convergence flags on the host).  Returns
+ * MERA_ENUMERIC for non-finite input or when the iteration does not reach an
+ * isometry (rank-deficient env); `out_d` is still written.  iters_out (host
+ * pointer, nullable) receives the number of iterations used. */
+int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* out_d,
+                      int32_t* iters_out, void* ws_d, size_t ws_bytes, void* hip_stream);
+
+/* Fixed point of the scale-invariant descending superoperator (Sec. II.B):
+ * `iters` steps of rho <- D_AVG(rho), rho <- (rho + rho^T)/2, rho <- rho/tr(rho)
+ * with D in `precision` and the symmetrisation and renormalisation in FP64.
+ * rho_d (d^6) holds the warm start on entry and the result on exit.
+ * resid_d (device, nullable, 1 double) receives ||rho_k - rho_{k-1}||_F /
+ * ||rho_k||_F of the last step.  layer->din must equal layer->dout. */
+int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int precision,
+                         double* resid_d, void* ws_d, size_t ws_bytes, void* hip_stream);
+
+/* Energy (Sec. II.B): e = tr(h rho) = sum_ij h_ij rho_ji for n x n matrices
+ * (n = d^3), FP64 with a fixed reduction order (bitwise reproducible).
+ * e_d: device pointer to one double.  Needs no workspace. */
+int mera_energy(const double* h_d, const double* rho_d, int64_t n, double* e_d, void* hip_stream);
+
+/* Three-site Hamiltonian density of the transverse-field Ising chain
+ * (Sec. II, Eq. ham; three-site regrouping of Sec. II.B):
+ *   h2 = -X(x)X - (g/2)(Z(x)1 + 1(x)Z),  h3 = (h2(x)1 + 1(x)h2)/2,
+ * with the field g split evenly over the two bonds of each site.  Writes the
+ * shifted density h3 - c*1 (8x8, row-major, host memory) and c = lambda_max(h3),
+ * so that the written operator is negative semidefinite.  Pure host function. */
+int mera_tfim_hamiltonian(double field, double* h_host /* 64 doubles */, double* shift_host);
+
+/* Workspace in bytes needed by `op` for the given shape, precision and
+ * placement (placement is ignored where it does not matter).  For
+ * MERA_OP_POLAR, din = rows and dout = cols.  Returns 0 for invalid
+ * arguments.  Pure host function. */
+size_t mera_workspace_bytes(int op, int32_t din, int32_t dout, int precision, int placement);
+
+/* Static text for a status code. */
+const char* mera_strerror(int status);
+
+/* Text of the last error seen on this thread (HIP error string or argument
+ * check), empty if none. */
+const char* mera_last_error(void);
+
+/* Double-precision flops of the schedule executed by `op` (multiply-add = 2),
+ * for throughput accounting; 0 for invalid arguments.  Pure host function. */
+double mera_flops(int op, int32_t din, int32_t dout, int placement);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MERA_H */

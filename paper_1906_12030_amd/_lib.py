@@ -1,0 +1,125 @@
+"""ctypes binding of libmera.so (include/mera.h).
+
+Argument marshalling only: every numerical step runs in the HIP library.  The
+library is loaded from this package directory; if it is missing, importing the
+binding raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmera.so")
+
+MERA_OK, MERA_EINVAL, MERA_ESHAPE, MERA_EWORKSPACE, MERA_EDEVICE, MERA_ENUMERIC, MERA_ENOTCONV = range(7)
+MERA_LEFT, MERA_RIGHT, MERA_AVG = 0, 1, 2
+MERA_FP64, MERA_FP32, MERA_BF16X3 = 0, 1, 2
+(MERA_OP_ASCEND, MERA_OP_DESCEND, MERA_OP_ENV_U, MERA_OP_ENV_W, MERA_OP_POLAR,
+ MERA_OP_FIXED_POINT, MERA_OP_ENERGY) = range(7)
+
+EXPORTED = (
+    "mera_ascend", "mera_descend", "mera_env_u", "mera_env_w", "mera_polar_update",
+    "mera_fixed_point_rho", "mera_energy", "mera_tfim_hamiltonian", "mera_workspace_bytes",
+    "mera_strerror", "mera_last_error", "mera_flops",
+)
+
+
+class MeraLayer(ctypes.Structure):
+    _fields_ = [("din", ctypes.c_int32), ("dout", ctypes.c_int32),
+                ("u_d", ctypes.c_void_p), ("w_d", ctypes.c_void_p)]
+
+
+class MeraError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libmera.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1906_12030_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+    lp = ctypes.POINTER(MeraLayer)
+    lib.mera_ascend.argtypes = [lp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
+    lib.mera_descend.argtypes = [lp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
+    lib.mera_env_u.argtypes = [lp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
+    lib.mera_env_w.argtypes = [lp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
+    lib.mera_polar_update.argtypes = [vp, i64, i64, vp, ctypes.POINTER(i32), vp, sz, vp]
+    lib.mera_fixed_point_rho.argtypes = [lp, vp, i32, ctypes.c_int, vp, vp, sz, vp]
+    lib.mera_energy.argtypes = [vp, vp, i64, vp, vp]
+    lib.mera_tfim_hamiltonian.argtypes = [dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    lib.mera_workspace_bytes.argtypes = [ctypes.c_int, i32, i32, ctypes.c_int, ctypes.c_int]
+    lib.mera_workspace_bytes.restype = sz
+    lib.mera_flops.argtypes = [ctypes.c_int, i32, i32, ctypes.c_int]
+    lib.mera_flops.restype = dbl
+    lib.mera_strerror.argtypes = [ctypes.c_int]
+    lib.mera_strerror.restype = ctypes.c_char_p
+    lib.mera_last_error.argtypes = []
+    lib.mera_last_error.restype = ctypes.c_char_p
+    for name in ("mera_ascend", "mera_descend", "mera_env_u", "mera_env_w", "mera_polar_update",
+                 "mera_fixed_point_rho", "mera_energy", "mera_tfim_hamiltonian"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(status: int, where: str) -> None:
+    if status != MERA_OK:
+        lib = load()
+        detail = lib.mera_strerror(status).decode()
+        last = lib.mera_last_error().decode()
+        raise MeraError(status, where, f"{detail} ({last})" if last else detail)
+
+
+def mera_ascend(layer, h_in_d, h_out_d, placement, precision, ws_d, ws_bytes, stream):
+    return load().mera_ascend(ctypes.byref(layer), h_in_d, h_out_d, placement, precision, ws_d, ws_bytes, stream)
+
+
+def mera_descend(layer, rho_in_d, rho_out_d, placement, precision, ws_d, ws_bytes, stream):
+    return load().mera_descend(ctypes.byref(layer), rho_in_d, rho_out_d, placement, precision, ws_d, ws_bytes, stream)
+
+
+def mera_env_u(layer, h_d, rho_d, env_d, placement, precision, ws_d, ws_bytes, stream):
+    return load().mera_env_u(ctypes.byref(layer), h_d, rho_d, env_d, placement, precision, ws_d, ws_bytes, stream)
+
+
+def mera_env_w(layer, h_d, rho_d, env_d, placement, precision, ws_d, ws_bytes, stream):
+    return load().mera_env_w(ctypes.byref(layer), h_d, rho_d, env_d, placement, precision, ws_d, ws_bytes, stream)
+
+
+def mera_polar_update(env_d, rows, cols, out_d, ws_d, ws_bytes, stream):
+    it = ctypes.c_int32(0)
+    st = load().mera_polar_update(env_d, rows, cols, out_d, ctypes.byref(it), ws_d, ws_bytes, stream)
+    return st, it.value
+
+
+def mera_fixed_point_rho(layer, rho_d, iters, precision, resid_d, ws_d, ws_bytes, stream):
+    return load().mera_fixed_point_rho(ctypes.byref(layer), rho_d, iters, precision, resid_d, ws_d, ws_bytes, stream)
+
+
+def mera_energy(h_d, rho_d, n, e_d, stream):
+    return load().mera_energy(h_d, rho_d, n, e_d, stream)
+
+
+def mera_tfim_hamiltonian(field):
+    h = (ctypes.c_double * 64)()
+    c = ctypes.c_double(0.0)
+    st = load().mera_tfim_hamiltonian(field, h, ctypes.byref(c))
+    return st, list(h), c.value
+
+
+def mera_workspace_bytes(op, din, dout, precision, placement):
+    return int(load().mera_workspace_bytes(op, din, dout, precision, placement))
+
+
+def mera_flops(op, din, dout, placement):
+    return float(load().mera_flops(op, din, dout, placement))

@@ -1,0 +1,746 @@
+// C ABI of the MERA hot path: argument checks, workspace layout and the
+// contraction schedules of the ascending / descending superoperators and the
+// environments, run on the contraction engine (contract.hip, contract_b3.hip).
+//
+// Network (one causal cone; Sec. II.B, Fig. 4).  Leg labels used below:
+//   fine legs, ket p q r s, bra P Q R S (dimension din)
+//   upper legs of the two disentanglers, ket a b | c d, bra A B | C D (din)
+//   outer legs of the side isometries x, y (din; traced between ket and bra)
+//   coarse legs, ket i j k, bra I J K (dout)
+// Ket tensors: uL = u[p q a b], uR = u[r s c d], wL = w[x a i], wC = w[b c j],
+// wR = w[d y k]; bra tensors are the same with capital letters except the
+// traced fine leg (s for the left window, p for the right window) and x, y.
+// Left window: fine legs (p q r | P Q R), s traced.  Right window:
+// (q r s | Q R S), p traced.
+//
+// Schedule of D (both placements share the first three steps):
+//   Lp[a i A I] = w[x a i] w[x A I]          Rp[d k D K] = w[d y k] w[D y K]
+//   X1[a j k A J K] = Lp . rho               X[j a d A D J] = X1 . Rp       (chi^8)
+//   N[r s b d j] = w[b c j] u[r s c d]       M[p q c a j] = u[p q a b] w[b c j]
+//   left :  Y = N . X  (sum d j)  -> [r s b a A D J]                          chi^9
+//           Z = Y . N' (sum s D J, N' = N with bra legs) -> [r a b A B R]     chi^9
+//           W1 = Z . uL (sum a b) -> [p q r A B R];  D_L = W1 . uL' (A B)    chi^8
+//   right:  T1 = M . X (sum a j) -> [p q c d A D J]                          chi^9
+//           ZR = T1 . M' (sum p A J) -> [q c d D C Q]                         chi^9
+//           W2 = ZR . uR (sum c d) -> [q r s C D Q]; D_R = W2 . uR' (C D)    chi^8
+// A runs the same steps in reverse (adjoint) order; the environments are the
+// reverse-mode derivatives of e = tr(h D(rho)) with respect to the ket copies.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mera.h"
+#include "engine.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_err(const std::string& s) { g_last_error = s; }
+
+using mera::Arith;
+using mera::LabelDims;
+
+// Bump allocator over the caller's workspace; in dry mode it only measures.
+struct Ctx {
+  Arith ar = Arith::F64;
+  LabelDims dims;
+  hipStream_t s = nullptr;
+  bool dry = true;
+  char* base = nullptr;
+  size_t off = 0;
+  double flops = 0.0;
+  hipError_t err = hipSuccess;
+
+  size_t elem() const { return ar == Arith::F64 ? 8 : 4; }
+  // reserve `count` elements of `bytes_per` bytes, 256-byte aligned
+  void* take(size_t count, size_t bytes_per) {
+    off = (off + 255) & ~size_t(255);
+    void* p = dry ? nullptr : base + off;
+    off += count * bytes_per;
+    return p;
+  }
+  void* take_t(size_t count) { return take(count, elem()); }
+  double* take_d(size_t count) { return static_cast<double*>(take(count, 8)); }
+
+  // C = alpha * A . B + beta * C   (A, B of the working type; C of the working type or double)
+  void c(const void* A, const char* la, const void* B, const char* lb, void* C, const char* lc,
+         bool c_f64, double alpha, double beta) {
+    if (dry) {
+      flops += mera::contract_flops(dims, la, lb, lc);
+      return;
+    }
+    if (err != hipSuccess) return;
+    const bool cf = (ar == Arith::F64) ? true : c_f64;
+    err = mera::contract(ar, dims, A, la, B, lb, C, lc, cf, alpha, beta, s, &flops);
+    if (err != hipSuccess)
+      set_err(std::string("contract ") + la + "," + lb + "->" + lc + ": " + hipGetErrorString(err));
+  }
+  void check(hipError_t e, const char* what) {
+    if (dry || err != hipSuccess) return;
+    if (e != hipSuccess) {
+      err = e;
+      set_err(std::string(what) + ": " + hipGetErrorString(e));
+    }
+  }
+};
+
+int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  while (e-- > 0) r *= b;
+  return r;
+}
+
+// Layer tensors in the working type (converted copies for F32 / B3).
+struct LayerT {
+  const void* u;
+  const void* w;
+};
+
+LayerT working_layer(Ctx& cx, const mera_layer* L) {
+  const int64_t din = L->din, dout = L->dout;
+  if (cx.ar == Arith::F64) return {L->u_d, L->w_d};
+  float* uf = static_cast<float*>(cx.take(ipow(din, 4), 4));
+  float* wf = static_cast<float*>(cx.take(din * din * dout, 4));
+  if (!cx.dry) {
+    cx.check(mera::launch_to_f32(L->u_d, uf, ipow(din, 4), cx.s), "to_f32(u)");
+    cx.check(mera::launch_to_f32(L->w_d, wf, din * din * dout, cx.s), "to_f32(w)");
+  }
+  return {uf, wf};
+}
+
+// A dout^6 / din^6 FP64 operand in the working type.
+const void* working_op(Ctx& cx, const double* x, int64_t n) {
+  if (cx.ar == Arith::F64) return x;
+  float* xf = static_cast<float*>(cx.take(n, 4));
+  if (!cx.dry) cx.check(mera::launch_to_f32(x, xf, n, cx.s), "to_f32(op)");
+  return xf;
+}
+
+void set_dims(Ctx& cx, int din, int dout) {
+  cx.dims = LabelDims();
+  cx.dims.set("pqrsPQRSabcdABCDxy", din);
+  cx.dims.set("ijkIJK", dout);
+}
+
+// Shared small tensors of one layer.
+struct Pieces {
+  void *Lp, *Rp, *N, *M;
+};
+
+Pieces build_pieces(Ctx& cx, const LayerT& t, int64_t din, int64_t dout) {
+  Pieces pc;
+  pc.Lp = cx.take_t(din * din * dout * dout);
+  pc.Rp = cx.take_t(din * din * dout * dout);
+  pc.N = cx.take_t(ipow(din, 4) * dout);
+  pc.M = cx.take_t(ipow(din, 4) * dout);
+  cx.c(t.w, "xai", t.w, "xAI", pc.Lp, "aiAI", false, 1.0, 0.0);
+  cx.c(t.w, "dyk", t.w, "DyK", pc.Rp, "dkDK", false, 1.0, 0.0);
+  cx.c(t.w, "bcj", t.u, "rscd", pc.N, "rsbdj", false, 1.0, 0.0);
+  cx.c(t.u, "pqab", t.w, "bcj", pc.M, "pqcaj", false, 1.0, 0.0);
+  return pc;
+}
+
+// X[j a d A D J] = sum Lp[a i A I] rho[i j k I J K] Rp[d k D K]; keeps X1 = Lp.rho.
+void build_x(Ctx& cx, const Pieces& pc, const void* rho, void* X1, void* X) {
+  cx.c(pc.Lp, "aiAI", rho, "ijkIJK", X1, "ajkAJK", false, 1.0, 0.0);
+  cx.c(X1, "ajkAJK", pc.Rp, "dkDK", X, "jadADJ", false, 1.0, 0.0);
+}
+
+struct Bufs {
+  void* big;   // din^6 * dout
+  void* mid;   // din^6
+  void* mid2;  // din^6
+};
+
+Bufs take_bufs(Ctx& cx, int64_t din, int64_t dout) {
+  Bufs b;
+  b.big = cx.take_t(ipow(din, 6) * dout);
+  b.mid = cx.take_t(ipow(din, 6));
+  b.mid2 = cx.take_t(ipow(din, 6));
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// D
+// ---------------------------------------------------------------------------
+int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_out,
+                int placement) {
+  const int64_t din = L->din, dout = L->dout;
+  set_dims(cx, (int)din, (int)dout);
+  LayerT t = working_layer(cx, L);
+  const void* rho = working_op(cx, rho_in, ipow(dout, 6));
+  Pieces pc = build_pieces(cx, t, din, dout);
+  void* X1 = cx.take_t(din * din * ipow(dout, 4));
+  void* X = cx.take_t(ipow(din, 4) * dout * dout);
+  Bufs b = take_bufs(cx, din, dout);
+  build_x(cx, pc, rho, X1, X);
+  const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
+  bool first = true;
+  if (placement != MERA_RIGHT) {
+    cx.c(pc.N, "rsbdj", X, "jadADJ", b.big, "rsbaADJ", false, 1.0, 0.0);
+    cx.c(b.big, "rsbaADJ", pc.N, "RsBDJ", b.mid, "rabABR", false, 1.0, 0.0);
+    cx.c(b.mid, "rabABR", t.u, "pqab", b.mid2, "pqrABR", false, 1.0, 0.0);
+    cx.c(b.mid2, "pqrABR", t.u, "PQAB", rho_out, "pqrPQR", true, wgt, 0.0);
+    first = false;
+  }
+  if (placement != MERA_LEFT) {
+    cx.c(pc.M, "pqcaj", X, "jadADJ", b.big, "pqcdADJ", false, 1.0, 0.0);
+    cx.c(b.big, "pqcdADJ", pc.M, "pQCAJ", b.mid, "qcdDCQ", false, 1.0, 0.0);
+    cx.c(b.mid, "qcdDCQ", t.u, "rscd", b.mid2, "qrsCDQ", false, 1.0, 0.0);
+    cx.c(b.mid2, "qrsCDQ", t.u, "RSCD", rho_out, "qrsQRS", true, wgt, first ? 0.0 : 1.0);
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// A (adjoint order of D)
+// ---------------------------------------------------------------------------
+int run_ascend(Ctx& cx, const mera_layer* L, const double* h_in, double* h_out, int placement) {
+  const int64_t din = L->din, dout = L->dout;
+  set_dims(cx, (int)din, (int)dout);
+  LayerT t = working_layer(cx, L);
+  const void* o = working_op(cx, h_in, ipow(din, 6));
+  Pieces pc = build_pieces(cx, t, din, dout);
+  void* Xb = cx.take_t(ipow(din, 4) * dout * dout);
+  void* Z1 = cx.take_t(din * din * ipow(dout, 4));
+  Bufs b = take_bufs(cx, din, dout);
+  const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
+  bool first = true;
+  if (placement != MERA_RIGHT) {
+    cx.c(o, "pqrPQR", t.u, "PQAB", b.mid2, "pqrABR", false, wgt, 0.0);
+    cx.c(b.mid2, "pqrABR", t.u, "pqab", b.mid, "rabABR", false, 1.0, 0.0);
+    cx.c(b.mid, "rabABR", pc.N, "RsBDJ", b.big, "rsbaADJ", false, 1.0, 0.0);
+    cx.c(pc.N, "rsbdj", b.big, "rsbaADJ", Xb, "jadADJ", false, 1.0, 0.0);
+    first = false;
+  }
+  if (placement != MERA_LEFT) {
+    cx.c(o, "qrsQRS", t.u, "RSCD", b.mid2, "qrsCDQ", false, wgt, 0.0);
+    cx.c(b.mid2, "qrsCDQ", t.u, "rscd", b.mid, "qcdDCQ", false, 1.0, 0.0);
+    cx.c(b.mid, "qcdDCQ", pc.M, "pQCAJ", b.big, "pqcdADJ", false, 1.0, 0.0);
+    cx.c(pc.M, "pqcaj", b.big, "pqcdADJ", Xb, "jadADJ", false, 1.0, first ? 0.0 : 1.0);
+  }
+  cx.c(Xb, "jadADJ", pc.Rp, "dkDK", Z1, "ajkAJK", false, 1.0, 0.0);
+  cx.c(Z1, "ajkAJK", pc.Lp, "aiAI", h_out, "ijkIJK", true, 1.0, 0.0);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Environments: reverse mode of e = tr(h D(rho)) w.r.t. the ket copies.
+// The cotangent of D[f, g] is h[g, f]: h is read with its row legs labelled as
+// bra legs ("PQRpqr" for the left window).
+// ---------------------------------------------------------------------------
+int run_env(Ctx& cx, const mera_layer* L, const double* h_in, const double* rho_in, double* env,
+            int placement, bool want_u) {
+  const int64_t din = L->din, dout = L->dout;
+  set_dims(cx, (int)din, (int)dout);
+  LayerT t = working_layer(cx, L);
+  const void* h = working_op(cx, h_in, ipow(din, 6));
+  const void* rho = working_op(cx, rho_in, ipow(dout, 6));
+  Pieces pc = build_pieces(cx, t, din, dout);
+  void* X1 = cx.take_t(din * din * ipow(dout, 4));
+  void* X = cx.take_t(ipow(din, 4) * dout * dout);
+  Bufs b = take_bufs(cx, din, dout);
+  void* dN = cx.take_t(ipow(din, 4) * dout);
+  void* dM = cx.take_t(ipow(din, 4) * dout);
+  void* dX = want_u ? nullptr : cx.take_t(ipow(din, 4) * dout * dout);
+  void* V1 = want_u ? nullptr : cx.take_t(din * din * ipow(dout, 4));
+  void* dLp = want_u ? nullptr : cx.take_t(din * din * dout * dout);
+  void* dRp = want_u ? nullptr : cx.take_t(din * din * dout * dout);
+  // env accumulators: written in FP64 directly by the final contractions
+  build_x(cx, pc, rho, X1, X);
+  const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
+  bool first_env = true;
+  bool first_dx = true;
+  auto acc_env = [&](const void* A, const char* la, const void* B, const char* lb, const char* lc) {
+    cx.c(A, la, B, lb, env, lc, true, 1.0, first_env ? 0.0 : 1.0);
+    first_env = false;
+  };
+  if (placement != MERA_RIGHT) {
+    // cotangent of the left window through the bra and ket copies of uL
+    cx.c(h, "PQRpqr", t.u, "PQAB", b.mid2, "pqrABR", false, wgt, 0.0);  // G1
+    if (want_u) {
+      // forward Z = (N . X) . N' for the derivative of the closing ket uL
+      cx.c(pc.N, "rsbdj", X, "jadADJ", b.big, "rsbaADJ", false, 1.0, 0.0);
+      cx.c(b.big, "rsbaADJ", pc.N, "RsBDJ", b.mid, "rabABR", false, 1.0, 0.0);
+      acc_env(b.mid2, "pqrABR", b.mid, "rabABR", "pqab");
+    }
+    cx.c(b.mid2, "pqrABR", t.u, "pqab", b.mid, "rabABR", false, 1.0, 0.0);   // G2
+    cx.c(b.mid, "rabABR", pc.N, "RsBDJ", b.big, "rsbaADJ", false, 1.0, 0.0);  // G3
+    cx.c(b.big, "rsbaADJ", X, "jadADJ", dN, "rsbdj", false, 1.0, 0.0);        // dN
+    if (want_u) {
+      acc_env(dN, "rsbdj", t.w, "bcj", "rscd");  // uR inside N
+    } else {
+      acc_env(dN, "rsbdj", t.u, "rscd", "bcj");  // wC inside N
+      cx.c(pc.N, "rsbdj", b.big, "rsbaADJ", dX, "jadADJ", false, 1.0, 0.0);
+      first_dx = false;
+    }
+  }
+  if (placement != MERA_LEFT) {
+    cx.c(h, "QRSqrs", t.u, "RSCD", b.mid2, "qrsCDQ", false, wgt, 0.0);  // H1
+    if (want_u) {
+      cx.c(pc.M, "pqcaj", X, "jadADJ", b.big, "pqcdADJ", false, 1.0, 0.0);
+      cx.c(b.big, "pqcdADJ", pc.M, "pQCAJ", b.mid, "qcdDCQ", false, 1.0, 0.0);
+      acc_env(b.mid2, "qrsCDQ", b.mid, "qcdDCQ", "rscd");
+    }
+    cx.c(b.mid2, "qrsCDQ", t.u, "rscd", b.mid, "qcdDCQ", false, 1.0, 0.0);   // H2
+    cx.c(b.mid, "qcdDCQ", pc.M, "pQCAJ", b.big, "pqcdADJ", false, 1.0, 0.0);  // H3
+    cx.c(b.big, "pqcdADJ", X, "jadADJ", dM, "pqcaj", false, 1.0, 0.0);        // dM
+    if (want_u) {
+      acc_env(dM, "pqcaj", t.w, "bcj", "pqab");  // uL inside M
+    } else {
+      acc_env(dM, "pqcaj", t.u, "pqab", "bcj");  // wC inside M
+      cx.c(pc.M, "pqcaj", b.big, "pqcdADJ", dX, "jadADJ", false, 1.0, first_dx ? 0.0 : 1.0);
+      first_dx = false;
+    }
+  }
+  if (!want_u) {
+    // isometries inside Lp and Rp (ket copies wL = w[x a i], wR = w[d y k])
+    cx.c(dX, "jadADJ", pc.Rp, "dkDK", V1, "ajkAJK", false, 1.0, 0.0);
+    cx.c(V1, "ajkAJK", rho, "ijkIJK", dLp, "aiAI", false, 1.0, 0.0);
+    acc_env(dLp, "aiAI", t.w, "xAI", "xai");
+    cx.c(X1, "ajkAJK", dX, "jadADJ", dRp, "dkDK", false, 1.0, 0.0);
+    acc_env(dRp, "dkDK", t.w, "DyK", "dyk");
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// checks
+// ---------------------------------------------------------------------------
+int check_layer(const mera_layer* L) {
+  if (!L) {
+    set_err("layer is null");
+    return MERA_EINVAL;
+  }
+  if (!L->u_d || !L->w_d) {
+    set_err("layer tensor pointer is null");
+    return MERA_EINVAL;
+  }
+  if (L->din < 1 || L->dout < 1) {
+    set_err("dimensions must be positive");
+    return MERA_ESHAPE;
+  }
+  if ((int64_t)L->dout > (int64_t)L->din * L->din) {
+    set_err("dout > din^2: no isometry exists");
+    return MERA_ESHAPE;
+  }
+  if (ipow(L->din, 6) * L->dout >= (int64_t(1) << 40)) {
+    set_err("layer too large");
+    return MERA_ESHAPE;
+  }
+  return MERA_OK;
+}
+
+int check_enum(int placement, int precision) {
+  if (placement < MERA_LEFT || placement > MERA_AVG) {
+    set_err("placement out of range");
+    return MERA_EINVAL;
+  }
+  if (precision < MERA_FP64 || precision > MERA_BF16X3) {
+    set_err("precision out of range");
+    return MERA_EINVAL;
+  }
+  return MERA_OK;
+}
+
+Arith arith_of(int precision) {
+  return precision == MERA_FP64 ? Arith::F64 : precision == MERA_FP32 ? Arith::F32 : Arith::B3;
+}
+
+template <typename F>
+int run_checked(Ctx& cx, void* ws, size_t ws_bytes, void* stream, F&& body) {
+  // dry pass for the size, then the real pass
+  Ctx dry = cx;
+  dry.dry = true;
+  dry.off = 0;
+  body(dry);
+  if (ws_bytes < dry.off) {
+    set_err("workspace too small: need " + std::to_string(dry.off) + " bytes");
+    return MERA_EWORKSPACE;
+  }
+  if (dry.off > 0 && !ws) {
+    set_err("workspace pointer is null");
+    return MERA_EINVAL;
+  }
+  if (reinterpret_cast<uintptr_t>(ws) % 256) {
+    set_err("workspace must be 256-byte aligned");
+    return MERA_EINVAL;
+  }
+  cx.dry = false;
+  cx.base = static_cast<char*>(ws);
+  cx.off = 0;
+  cx.s = static_cast<hipStream_t>(stream);
+  body(cx);
+  if (cx.err != hipSuccess) return MERA_EDEVICE;
+  return MERA_OK;
+}
+
+// Polar update by the Newton-Schulz iteration X <- X (3 I - X^T X) / 2 started
+// from Y / ||Y||_F (all singular values in (0, 1]), which converges to the
+// orthogonal polar factor U V^T of Y = U S V^T.
+struct PolarWs {
+  double *x, *xn, *g, *partial, *scal;
+};
+PolarWs polar_layout(Ctx& cx, int64_t rows, int64_t cols) {
+  PolarWs p;
+  p.x = cx.take_d(rows * cols);
+  p.xn = cx.take_d(rows * cols);
+  p.g = cx.take_d(cols * cols);
+  p.partial = cx.take_d(mera::kReduceBlocks);
+  p.scal = cx.take_d(4);
+  return p;
+}
+
+constexpr int kPolarMaxIter = 100;
+
+}  // namespace
+
+extern "C" {
+
+const char* mera_strerror(int status) {
+  switch (status) {
+    case MERA_OK: return "ok";
+    case MERA_EINVAL: return "invalid argument";
+    case MERA_ESHAPE: return "inconsistent shape";
+    case MERA_EWORKSPACE: return "workspace too small";
+    case MERA_EDEVICE: return "device (HIP) error";
+    case MERA_ENUMERIC: return "numerical failure";
+    case MERA_ENOTCONV: return "not converged";
+    default: return "unknown status";
+  }
+}
+
+const char* mera_last_error(void) { return g_last_error.c_str(); }
+
+int mera_descend(const mera_layer* layer, const double* rho_in_d, double* rho_out_d, int placement,
+                 int precision, void* ws_d, size_t ws_bytes, void* hip_stream) {
+  int st = check_layer(layer);
+  if (st) return st;
+  if ((st = check_enum(placement, precision))) return st;
+  if (!rho_in_d || !rho_out_d) {
+    set_err("null tensor pointer");
+    return MERA_EINVAL;
+  }
+  Ctx cx;
+  cx.ar = arith_of(precision);
+  return run_checked(cx, ws_d, ws_bytes, hip_stream,
+                     [&](Ctx& c) { run_descend(c, layer, rho_in_d, rho_out_d, placement); });
+}
+
+int mera_ascend(const mera_layer* layer, const double* h_in_d, double* h_out_d, int placement,
+                int precision, void* ws_d, size_t ws_bytes, void* hip_stream) {
+  int st = check_layer(layer);
+  if (st) return st;
+  if ((st = check_enum(placement, precision))) return st;
+  if (!h_in_d || !h_out_d) {
+    set_err("null tensor pointer");
+    return MERA_EINVAL;
+  }
+  Ctx cx;
+  cx.ar = arith_of(precision);
+  return run_checked(cx, ws_d, ws_bytes, hip_stream,
+                     [&](Ctx& c) { run_ascend(c, layer, h_in_d, h_out_d, placement); });
+}
+
+int mera_env_u(const mera_layer* layer, const double* h_d, const double* rho_d, double* env_u_d,
+               int placement, int precision, void* ws_d, size_t ws_bytes, void* hip_stream) {
+  int st = check_layer(layer);
+  if (st) return st;
+  if ((st = check_enum(placement, precision))) return st;
+  if (!h_d || !rho_d || !env_u_d) {
+    set_err("null tensor pointer");
+    return MERA_EINVAL;
+  }
+  Ctx cx;
+  cx.ar = arith_of(precision);
+  return run_checked(cx, ws_d, ws_bytes, hip_stream, [&](Ctx& c) {
+    run_env(c, layer, h_d, rho_d, env_u_d, placement, true);
+  });
+}
+
+int mera_env_w(const mera_layer* layer, const double* h_d, const double* rho_d, double* env_w_d,
+               int placement, int precision, void* ws_d, size_t ws_bytes, void* hip_stream) {
+  int st = check_layer(layer);
+  if (st) return st;
+  if ((st = check_enum(placement, precision))) return st;
+  if (!h_d || !rho_d || !env_w_d) {
+    set_err("null tensor pointer");
+    return MERA_EINVAL;
+  }
+  Ctx cx;
+  cx.ar = arith_of(precision);
+  return run_checked(cx, ws_d, ws_bytes, hip_stream, [&](Ctx& c) {
+    run_env(c, layer, h_d, rho_d, env_w_d, placement, false);
+  });
+}
+
+int mera_energy(const double* h_d, const double* rho_d, int64_t n, double* e_d, void* hip_stream) {
+  if (!h_d || !rho_d || !e_d) {
+    set_err("null tensor pointer");
+    return MERA_EINVAL;
+  }
+  if (n < 1 || n > (int64_t(1) << 20)) {
+    set_err("matrix order out of range");
+    return MERA_ESHAPE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // one workgroup in a fixed order: needs no scratch and is bitwise reproducible
+  hipError_t e = mera::launch_trace_product_small(h_d, rho_d, n, e_d, s);
+  if (e != hipSuccess) {
+    set_err(std::string("energy: ") + hipGetErrorString(e));
+    return MERA_EDEVICE;
+  }
+  return MERA_OK;
+}
+
+int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* out_d,
+                      int32_t* iters_out, void* ws_d, size_t ws_bytes, void* hip_stream) {
+  if (!env_d || !out_d) {
+    set_err("null tensor pointer");
+    return MERA_EINVAL;
+  }
+  if (rows < 1 || cols < 1 || rows < cols || rows * cols >= (int64_t(1) << 31)) {
+    set_err("polar needs rows >= cols >= 1");
+    return MERA_ESHAPE;
+  }
+  Ctx dry;
+  dry.dry = true;
+  polar_layout(dry, rows, cols);
+  if (ws_bytes < dry.off) {
+    set_err("workspace too small: need " + std::to_string(dry.off) + " bytes");
+    return MERA_EWORKSPACE;
+  }
+  if (!ws_d || reinterpret_cast<uintptr_t>(ws_d) % 256) {
+    set_err("workspace null or not 256-byte aligned");
+    return MERA_EINVAL;
+  }
+  Ctx cx;
+  cx.dry = false;
+  cx.base = static_cast<char*>(ws_d);
+  cx.s = static_cast<hipStream_t>(hip_stream);
+  PolarWs p = polar_layout(cx, rows, cols);
+  LabelDims dims;
+  dims.d['a'] = rows;
+  dims.d['b'] = cols;
+  dims.d['c'] = cols;
+  hipStream_t s = cx.s;
+  const int64_t n = rows * cols;
+  double host[2];
+  auto fail = [&](hipError_t e, const char* what) {
+    set_err(std::string("polar ") + what + ": " + hipGetErrorString(e));
+    return MERA_EDEVICE;
+  };
+  hipError_t e;
+  if ((e = mera::launch_reduce(4, env_d, nullptr, n, p.partial, p.scal, s))) return fail(e, "norm");
+  if ((e = hipMemcpyAsync(host, p.scal, sizeof(double), hipMemcpyDeviceToHost, s))) return fail(e, "copy");
+  if ((e = hipStreamSynchronize(s))) return fail(e, "sync");
+  if (!std::isfinite(host[0]) || host[0] <= 0.0) {
+    if ((e = mera::launch_fill(out_d, 0.0, n, s))) return fail(e, "fill");
+    hipStreamSynchronize(s);
+    set_err("polar: environment is zero or not finite");
+    return MERA_ENUMERIC;
+  }
+  if ((e = mera::launch_scale_by_rsqrt(env_d, p.x, p.scal, n, s))) return fail(e, "scale");
+  int it = 0;
+  bool conv = false;
+  for (it = 1; it <= kPolarMaxIter; ++it) {
+    if ((e = mera::contract(Arith::F64, dims, p.x, "ab", p.x, "ac", p.g, "bc", true, 1.0, 0.0, s)))
+      return fail(e, "gram");
+    if ((e = mera::launch_scale(p.x, p.xn, 1.5, n, s))) return fail(e, "scale");
+    if ((e = mera::contract(Arith::F64, dims, p.x, "ab", p.g, "bc", p.xn, "ac", true, -0.5, 1.0, s)))
+      return fail(e, "update");
+    if ((e = mera::launch_reduce(1, p.xn, p.x, n, p.partial, p.scal + 1, s))) return fail(e, "diff");
+    std::swap(p.x, p.xn);
+    if ((e = hipMemcpyAsync(host + 1, p.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s)))
+      return fail(e, "copy");
+    if ((e = hipStreamSynchronize(s))) return fail(e, "sync");
+    if (!std::isfinite(host[1])) break;
+    if (std::sqrt(host[1]) < 1e-13 * std::sqrt((double)cols)) {
+      conv = true;
+      break;
+    }
+  }
+  if (iters_out) *iters_out = it > kPolarMaxIter ? kPolarMaxIter : it;
+  // out = -X; then check that X reached an isometry: ||X||_F^2 = cols
+  if ((e = mera::launch_scale(p.x, out_d, -1.0, n, s))) return fail(e, "out");
+  if ((e = mera::launch_reduce(4, p.x, nullptr, n, p.partial, p.scal + 2, s))) return fail(e, "fro");
+  if ((e = hipMemcpyAsync(host, p.scal + 2, sizeof(double), hipMemcpyDeviceToHost, s)))
+    return fail(e, "copy");
+  if ((e = hipStreamSynchronize(s))) return fail(e, "sync");
+  if (!conv || !(std::fabs(host[0] - (double)cols) < 1e-8 * (double)cols)) {
+    set_err("polar: iteration did not reach an isometry (rank-deficient or non-finite environment)");
+    return MERA_ENUMERIC;
+  }
+  return MERA_OK;
+}
+
+int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int precision,
+                         double* resid_d, void* ws_d, size_t ws_bytes, void* hip_stream) {
+  int st = check_layer(si);
+  if (st) return st;
+  if ((st = check_enum(MERA_AVG, precision))) return st;
+  if (si->din != si->dout) {
+    set_err("fixed point needs din == dout");
+    return MERA_ESHAPE;
+  }
+  if (!rho_d || iters < 0) {
+    set_err("null density or negative iteration count");
+    return MERA_EINVAL;
+  }
+  const int64_t d = si->din;
+  const int64_t n = d * d * d;
+  Ctx cx;
+  cx.ar = arith_of(precision);
+  auto body = [&](Ctx& c) {
+    double* tmp = c.take_d(n * n);
+    double* prev = resid_d ? c.take_d(n * n) : nullptr;
+    double* partial = c.take_d(mera::kReduceBlocks);
+    double* scal = c.take_d(4);
+    const size_t mark = c.off;
+    for (int it = 0; it < iters; ++it) {
+      c.off = mark;  // the descend workspace is reused by every iteration
+      run_descend(c, si, rho_d, tmp, MERA_AVG);
+      if (c.dry) {
+        if (it > 0) break;  // size and flops of one iteration suffice in a dry pass
+        continue;
+      }
+      c.check(mera::launch_reduce(2, tmp, nullptr, n, partial, scal, c.s), "trace");
+      if (resid_d && it == iters - 1) c.check(hipMemcpyAsync(prev, rho_d, n * n * 8, hipMemcpyDeviceToDevice, c.s), "copy");
+      c.check(mera::launch_sym_normalize(tmp, rho_d, n, scal, c.s), "symmetrise");
+    }
+    if (!c.dry && resid_d) {
+      if (iters == 0) {
+        c.check(mera::launch_fill(resid_d, 0.0, 1, c.s), "fill");
+      } else {
+        c.check(mera::launch_reduce(1, rho_d, prev, n * n, partial, scal + 1, c.s), "diff");
+        c.check(mera::launch_reduce(4, rho_d, nullptr, n * n, partial, scal + 2, c.s), "norm");
+        c.check(mera::launch_sqrt_ratio(scal + 1, scal + 2, resid_d, c.s), "ratio");
+      }
+    }
+  };
+  int rc = run_checked(cx, ws_d, ws_bytes, hip_stream, body);
+  return rc;
+}
+
+int mera_tfim_hamiltonian(double field, double* h_host, double* shift_host) {
+  if (!h_host || !shift_host || !std::isfinite(field)) {
+    set_err("null pointer or non-finite field");
+    return MERA_EINVAL;
+  }
+  // Pauli X and Z on one spin; kron products written out index by index.
+  const double X[2][2] = {{0, 1}, {1, 0}}, Z[2][2] = {{1, 0}, {0, -1}};
+  double h2[4][4];
+  for (int i1 = 0; i1 < 2; ++i1)
+    for (int i2 = 0; i2 < 2; ++i2)
+      for (int j1 = 0; j1 < 2; ++j1)
+        for (int j2 = 0; j2 < 2; ++j2) {
+          const double d1 = i1 == j1 ? 1.0 : 0.0, d2 = i2 == j2 ? 1.0 : 0.0;
+          h2[i1 * 2 + i2][j1 * 2 + j2] =
+              -X[i1][j1] * X[i2][j2] - 0.5 * field * (Z[i1][j1] * d2 + d1 * Z[i2][j2]);
+        }
+  double h3[8][8];
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) {
+      const int i12 = i >> 1, i3 = i & 1, j12 = j >> 1, j3 = j & 1;  // (s1 s2) s3
+      const int i1 = i >> 2, i23 = i & 3, j1 = j >> 2, j23 = j & 3;  // s1 (s2 s3)
+      h3[i][j] = 0.5 * (h2[i12][j12] * (i3 == j3 ? 1.0 : 0.0) + (i1 == j1 ? 1.0 : 0.0) * h2[i23][j23]);
+    }
+  // largest eigenvalue by cyclic Jacobi rotations on a copy
+  double a[8][8];
+  std::memcpy(a, h3, sizeof(a));
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < 8; ++p)
+      for (int q = p + 1; q < 8; ++q) off += a[p][q] * a[p][q];
+    if (off < 1e-300) break;
+    for (int p = 0; p < 8; ++p)
+      for (int q = p + 1; q < 8; ++q) {
+        if (std::fabs(a[p][q]) < 1e-300) continue;
+        const double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 8; ++k) {  // columns p, q
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = c * akp - sn * akq;
+          a[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 8; ++k) {  // rows p, q
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = c * apk - sn * aqk;
+          a[q][k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  double lmax = a[0][0];
+  for (int i = 1; i < 8; ++i) lmax = std::fmax(lmax, a[i][i]);
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) h_host[i * 8 + j] = h3[i][j] - (i == j ? lmax : 0.0);
+  *shift_host = lmax;
+  return MERA_OK;
+}
+
+size_t mera_workspace_bytes(int op, int32_t din, int32_t dout, int precision, int placement) {
+  Ctx cx;
+  if (precision < MERA_FP64 || precision > MERA_BF16X3) return 0;
+  if (op == MERA_OP_ENERGY) return 0;
+  if (op == MERA_OP_POLAR) {
+    if (din < 1 || dout < 1 || din < dout) return 0;
+    cx.dry = true;
+    polar_layout(cx, din, dout);
+    return cx.off;
+  }
+  if (din < 1 || dout < 1 || (int64_t)dout > (int64_t)din * din) return 0;
+  if (placement < MERA_LEFT || placement > MERA_AVG) return 0;
+  mera_layer L{din, dout, reinterpret_cast<const double*>(256), reinterpret_cast<const double*>(256)};
+  cx.ar = arith_of(precision);
+  cx.dry = true;
+  const double* dummy = reinterpret_cast<const double*>(256);
+  double* out = reinterpret_cast<double*>(256);
+  switch (op) {
+    case MERA_OP_ASCEND: run_ascend(cx, &L, dummy, out, placement); break;
+    case MERA_OP_DESCEND: run_descend(cx, &L, dummy, out, placement); break;
+    case MERA_OP_ENV_U: run_env(cx, &L, dummy, dummy, out, placement, true); break;
+    case MERA_OP_ENV_W: run_env(cx, &L, dummy, dummy, out, placement, false); break;
+    case MERA_OP_FIXED_POINT: {
+      if (din != dout) return 0;
+      const int64_t n = (int64_t)din * din * din;
+      cx.take_d(n * n);
+      cx.take_d(n * n);
+      cx.take_d(mera::kReduceBlocks);
+      cx.take_d(4);
+      run_descend(cx, &L, dummy, out, MERA_AVG);
+      break;
+    }
+    default: return 0;
+  }
+  return cx.off;
+}
+
+double mera_flops(int op, int32_t din, int32_t dout, int placement) {
+  if (din < 1 || dout < 1 || (int64_t)dout > (int64_t)din * din) return 0.0;
+  if (placement < MERA_LEFT || placement > MERA_AVG) return 0.0;
+  mera_layer L{din, dout, reinterpret_cast<const double*>(256), reinterpret_cast<const double*>(256)};
+  Ctx cx;
+  cx.dry = true;
+  const double* dummy = reinterpret_cast<const double*>(256);
+  double* out = reinterpret_cast<double*>(256);
+  switch (op) {
+    case MERA_OP_ASCEND: run_ascend(cx, &L, dummy, out, placement); break;
+    case MERA_OP_DESCEND: run_descend(cx, &L, dummy, out, placement); break;
+    case MERA_OP_ENV_U: run_env(cx, &L, dummy, dummy, out, placement, true); break;
+    case MERA_OP_ENV_W: run_env(cx, &L, dummy, dummy, out, placement, false); break;
+    case MERA_OP_FIXED_POINT:
+      if (din != dout) return 0.0;
+      run_descend(cx, &L, dummy, out, MERA_AVG);  // per iteration
+      break;
+    default: return 0.0;
+  }
+  return cx.flops;
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+"""Torch-facing calls of the MERA hot path.
+
+PyTorch supplies device memory and the stream; every computation happens in
+libmera.so (through ``_lib``).  Tensors are float64, contiguous, on a HIP
+device.  Outputs and workspaces are allocated here with torch.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+
+PLACEMENTS = {"left": _lib.MERA_LEFT, "right": _lib.MERA_RIGHT, "avg": _lib.MERA_AVG,
+              "L": _lib.MERA_LEFT, "R": _lib.MERA_RIGHT, "AVG": _lib.MERA_AVG}
+PRECISIONS = {"fp64": _lib.MERA_FP64, "fp32": _lib.MERA_FP32, "bf16x3": _lib.MERA_BF16X3}
+
+
+def _dev(t: torch.Tensor) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if t.dtype != torch.float64:
+        raise TypeError("tensors must be float64")
+    return t.contiguous()
+
+
+class Layer:
+    """A MERA layer (u: din^4, w: din*din*dout) as device float64 tensors."""
+
+    def __init__(self, u: torch.Tensor, w: torch.Tensor):
+        self.u = _dev(u)
+        self.w = _dev(w)
+        self.din = int(self.w.shape[0])
+        self.dout = int(self.w.shape[2])
+        if tuple(self.u.shape) != (self.din,) * 4 or tuple(self.w.shape) != (self.din, self.din, self.dout):
+            raise ValueError("layer shapes: u must be din^4 and w din x din x dout")
+
+    def c(self) -> _lib.MeraLayer:
+        return _lib.MeraLayer(self.din, self.dout, self.u.data_ptr(), self.w.data_ptr())
+
+
+class Workspace:
+    """Grow-only device workspace, reused by calls on the same stream."""
+
+    def __init__(self):
+        self.buf: dict = {}
+
+    def get(self, nbytes: int, device) -> tuple[int, int]:
+        key = (torch.device(device).index,)
+        cur = self.buf.get(key)
+        if nbytes == 0:
+            return 0, 0
+        if cur is None or cur.numel() < nbytes:
+            self.buf[key] = None
+            cur = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+            self.buf[key] = cur
+        ptr = cur.data_ptr()
+        aligned = (ptr + 255) & ~255
+        return aligned, cur.numel() - (aligned - ptr)
+
+    def release(self):
+        self.buf.clear()
+
+
+WORKSPACE = Workspace()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _prec(precision) -> int:
+    return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+
+def _place(placement) -> int:
+    return PLACEMENTS[placement] if isinstance(placement, str) else int(placement)
+
+
+def ascend(layer: Layer, h: torch.Tensor, placement="avg", precision="fp64", out=None):
+    """A_P(h): din^6 -> dout^6 (Sec. II.B, Fig. 4a)."""
+    h = _dev(h)
+    p, q = _place(placement), _prec(precision)
+    if out is None:
+        out = torch.empty((layer.dout,) * 6, dtype=torch.float64, device=h.device)
+    nb = _lib.mera_workspace_bytes(_lib.MERA_OP_ASCEND, layer.din, layer.dout, q, p)
+    ws, wsb = WORKSPACE.get(nb, h.device)
+    _lib.check(_lib.mera_ascend(layer.c(), h.data_ptr(), out.data_ptr(), p, q, ws, wsb, _stream(h.device)), "mera_ascend")
+    return out
+
+
+def descend(layer: Layer, rho: torch.Tensor, placement="avg", precision="fp64", out=None):
+    """D_P(rho): dout^6 -> din^6 (Sec. II.B, Fig. 4b)."""
+    rho = _dev(rho)
+    p, q = _place(placement), _prec(precision)
+    if out is None:
+        out = torch.empty((layer.din,) * 6, dtype=torch.float64, device=rho.device)
+    nb = _lib.mera_workspace_bytes(_lib.MERA_OP_DESCEND, layer.din, layer.dout, q, p)
+    ws, wsb = WORKSPACE.get(nb, rho.device)
+    _lib.check(_lib.mera_descend(layer.c(), rho.data_ptr(), out.data_ptr(), p, q, ws, wsb, _stream(rho.device)), "mera_descend")
+    return out
+
+
+def env_u(layer: Layer, h: torch.Tensor, rho: torch.Tensor, placement="avg", precision="fp64", out=None):
+    """Environment of u (Sec. II.C, Fig. 4d): din^4."""
+    h, rho = _dev(h), _dev(rho)
+    p, q = _place(placement), _prec(precision)
+    if out is None:
+        out = torch.empty((layer.din,) * 4, dtype=torch.float64, device=h.device)
+    nb = _lib.mera_workspace_bytes(_lib.MERA_OP_ENV_U, layer.din, layer.dout, q, p)
+    ws, wsb = WORKSPACE.get(nb, h.device)
+    _lib.check(_lib.mera_env_u(layer.c(), h.data_ptr(), rho.data_ptr(), out.data_ptr(), p, q, ws, wsb, _stream(h.device)), "mera_env_u")
+    return out
+
+
+def env_w(layer: Layer, h: torch.Tensor, rho: torch.Tensor, placement="avg", precision="fp64", out=None):
+    """Environment of w (Sec. II.C, Fig. 4c): din x din x dout."""
+    h, rho = _dev(h), _dev(rho)
+    p, q = _place(placement), _prec(precision)
+    if out is None:
+        out = torch.empty((layer.din, layer.din, layer.dout), dtype=torch.float64, device=h.device)
+    nb = _lib.mera_workspace_bytes(_lib.MERA_OP_ENV_W, layer.din, layer.dout, q, p)
+    ws, wsb = WORKSPACE.get(nb, h.device)
+    _lib.check(_lib.mera_env_w(layer.c(), h.data_ptr(), rho.data_ptr(), out.data_ptr(), p, q, ws, wsb, _stream(h.device)), "mera_env_w")
+    return out
+
+
+def polar_update(env: torch.Tensor, rows: int, cols: int, out=None, check=True):
+    """-U V^T of env blocked as rows x cols (Sec. II.C, Fig. 5).  Returns (out, iterations, status)."""
+    env = _dev(env)
+    if out is None:
+        out = torch.empty(env.shape, dtype=torch.float64, device=env.device)
+    nb = _lib.mera_workspace_bytes(_lib.MERA_OP_POLAR, rows, cols, 0, 0)
+    ws, wsb = WORKSPACE.get(nb, env.device)
+    st, iters = _lib.mera_polar_update(env.data_ptr(), rows, cols, out.data_ptr(), ws, wsb, _stream(env.device))
+    if check:
+        _lib.check(st, "mera_polar_update")
+    return out, iters, st
+
+
+def update_u(env: torch.Tensor, check=True) -> torch.Tensor:
+    d = env.shape[0]
+    return polar_update(env, d * d, d * d, check=check)[0]
+
+
+def update_w(env: torch.Tensor, check=True) -> torch.Tensor:
+    din, _, dout = env.shape
+    return polar_update(env, din * din, dout, check=check)[0]
+
+
+def fixed_point_rho(si: Layer, rho: torch.Tensor, iters: int, precision="fp64", want_residual=False):
+    """In place: iters power-iteration steps of the scale-invariant D (Sec. II.B)."""
+    if not (rho.is_cuda and rho.dtype == torch.float64 and rho.is_contiguous()):
+        raise ValueError("rho must be a contiguous float64 GPU tensor (it is updated in place)")
+    q = _prec(precision)
+    resid = torch.zeros(1, dtype=torch.float64, device=rho.device) if want_residual else None
+    nb = _lib.mera_workspace_bytes(_lib.MERA_OP_FIXED_POINT, si.din, si.dout, q, _lib.MERA_AVG)
+    ws, wsb = WORKSPACE.get(nb, rho.device)
+    _lib.check(_lib.mera_fixed_point_rho(si.c(), rho.data_ptr(), int(iters), q,
+                                         resid.data_ptr() if resid is not None else None,
+                                         ws, wsb, _stream(rho.device)), "mera_fixed_point_rho")
+    return rho, resid
+
+
+def energy(h: torch.Tensor, rho: torch.Tensor) -> torch.Tensor:
+    """tr(h rho) as a one-element device tensor (Sec. II.B)."""
+    h, rho = _dev(h), _dev(rho)
+    n = int(round(h.numel() ** 0.5))
+    if n * n != h.numel() or rho.numel() != h.numel():
+        raise ValueError("h and rho must be n x n matrices of the same order")
+    e = torch.empty(1, dtype=torch.float64, device=h.device)
+    _lib.check(_lib.mera_energy(h.data_ptr(), rho.data_ptr(), n, e.data_ptr(), _stream(h.device)), "mera_energy")
+    return e
+
+
+def tfim_hamiltonian(field: float = 1.0, device="cuda"):
+    """Shifted three-site TFIM density (8x8 -> [2]*6) built by the library, and the shift."""
+    st, h, c = _lib.mera_tfim_hamiltonian(float(field))
+    _lib.check(st, "mera_tfim_hamiltonian")
+    return torch.tensor(h, dtype=torch.float64).reshape((2,) * 6).to(device), c
+
+
+def flops(op: str, din: int, dout: int, placement="avg") -> float:
+    ops = {"ascend": _lib.MERA_OP_ASCEND, "descend": _lib.MERA_OP_DESCEND, "env_u": _lib.MERA_OP_ENV_U,
+           "env_w": _lib.MERA_OP_ENV_W, "fixed_point_iter": _lib.MERA_OP_FIXED_POINT}
+    return _lib.mera_flops(ops[op], din, dout, _place(placement))

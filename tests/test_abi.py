@@ -1,0 +1,113 @@
+"""Host-side tests of the C ABI: exports, argument checks, workspace and flop accounting.
+
+These run without a GPU: every rejected call returns before any HIP call.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1906_12030_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libmera.so not built")
+    return _lib.load()
+
+
+def test_header_symbols_are_exported(lib):
+    hdr = open(os.path.join(ROOT, "include", "mera.h")).read()
+    names = set(re.findall(r"\b(mera_[a-z_0-9]+)\s*\(", hdr))
+    assert {"mera_ascend", "mera_descend", "mera_env_u", "mera_env_w", "mera_polar_update",
+            "mera_fixed_point_rho", "mera_energy"} <= names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(_lib.EXPORTED) == names
+
+
+def test_strerror(lib):
+    for st in range(7):
+        assert lib.mera_strerror(st)
+    assert b"unknown" in lib.mera_strerror(99)
+
+
+def _layer(din, dout, nonnull=True):
+    p = 4096 if nonnull else 0
+    return _lib.MeraLayer(din, dout, p, p)
+
+
+def test_invalid_arguments_rejected_before_device(lib):
+    fake = 4096  # never dereferenced: validation fails first
+    assert _lib.mera_descend(_layer(4, 17), fake, fake, 2, 0, fake, 1 << 40, None) == _lib.MERA_ESHAPE
+    assert _lib.mera_descend(_layer(4, 4, False), fake, fake, 2, 0, fake, 1 << 40, None) == _lib.MERA_EINVAL
+    assert _lib.mera_descend(_layer(4, 4), fake, fake, 3, 0, fake, 1 << 40, None) == _lib.MERA_EINVAL
+    assert _lib.mera_descend(_layer(4, 4), fake, fake, 2, 7, fake, 1 << 40, None) == _lib.MERA_EINVAL
+    assert _lib.mera_descend(_layer(4, 4), None, fake, 2, 0, fake, 1 << 40, None) == _lib.MERA_EINVAL
+    assert _lib.mera_ascend(_layer(0, 4), fake, fake, 2, 0, fake, 1 << 40, None) == _lib.MERA_ESHAPE
+    assert _lib.mera_env_u(_layer(3, 3), fake, None, fake, 2, 0, fake, 1 << 40, None) == _lib.MERA_EINVAL
+    assert _lib.mera_env_w(_layer(3, 10), fake, fake, fake, 2, 0, fake, 1 << 40, None) == _lib.MERA_ESHAPE
+    assert _lib.mera_fixed_point_rho(_layer(3, 4), fake, 5, 0, None, fake, 1 << 40, None) == _lib.MERA_ESHAPE
+    assert _lib.mera_fixed_point_rho(_layer(3, 3), fake, -1, 0, None, fake, 1 << 40, None) == _lib.MERA_EINVAL
+    st, _ = _lib.mera_polar_update(fake, 4, 9, fake, fake, 1 << 40, None)
+    assert st == _lib.MERA_ESHAPE
+    st, _ = _lib.mera_polar_update(None, 9, 4, fake, fake, 1 << 40, None)
+    assert st == _lib.MERA_EINVAL
+    assert _lib.mera_energy(fake, fake, 0, fake, None) == _lib.MERA_ESHAPE
+    assert lib.mera_last_error()
+
+
+def test_workspace_too_small_and_misaligned(lib):
+    fake = 4096
+    need = _lib.mera_workspace_bytes(_lib.MERA_OP_DESCEND, 4, 4, 0, 2)
+    assert need > 0
+    assert _lib.mera_descend(_layer(4, 4), fake, fake, 2, 0, fake, need - 1, None) == _lib.MERA_EWORKSPACE
+    assert _lib.mera_descend(_layer(4, 4), fake, fake, 2, 0, fake + 8, need, None) == _lib.MERA_EINVAL
+    npol = _lib.mera_workspace_bytes(_lib.MERA_OP_POLAR, 16, 4, 0, 0)
+    st, _ = _lib.mera_polar_update(fake, 16, 4, fake, fake, npol - 1, None)
+    assert st == _lib.MERA_EWORKSPACE
+
+
+def test_workspace_grows_with_bond_dimension(lib):
+    for op in (_lib.MERA_OP_ASCEND, _lib.MERA_OP_DESCEND, _lib.MERA_OP_ENV_U, _lib.MERA_OP_ENV_W):
+        for prec in (0, 1, 2):
+            sizes = [_lib.mera_workspace_bytes(op, d, d, prec, 2) for d in (2, 4, 8, 12, 16, 24)]
+            assert all(a < b for a, b in zip(sizes, sizes[1:])), (op, prec, sizes)
+    # the chi^7 intermediate dominates: FP64 at chi=24 needs about 24^7 * 8 bytes
+    ws = _lib.mera_workspace_bytes(_lib.MERA_OP_DESCEND, 24, 24, 0, 2)
+    assert 24 ** 7 * 8 < ws < 1.3 * 24 ** 7 * 8
+    ws32 = _lib.mera_workspace_bytes(_lib.MERA_OP_DESCEND, 24, 24, 1, 2)
+    assert 0.45 < ws32 / ws < 0.6
+    assert _lib.mera_workspace_bytes(_lib.MERA_OP_DESCEND, 4, 17, 0, 2) == 0
+    assert _lib.mera_workspace_bytes(99, 4, 4, 0, 2) == 0
+
+
+def test_flop_accounting_scales_as_chi9(lib):
+    """Executed flops: 8 chi^9 per D or A call (four chi^9 GEMMs) plus lower orders."""
+    for chi in (16, 24, 32):
+        for op in (_lib.MERA_OP_DESCEND, _lib.MERA_OP_ASCEND):
+            f = _lib.mera_flops(op, chi, chi, 2)
+            assert 8 * chi ** 9 < f < 8 * chi ** 9 * (1 + 8.0 / chi), (op, chi, f / chi ** 9)
+        fu = _lib.mera_flops(_lib.MERA_OP_ENV_U, chi, chi, 2)
+        fw = _lib.mera_flops(_lib.MERA_OP_ENV_W, chi, chi, 2)
+        assert 16 * chi ** 9 < fu < 16 * chi ** 9 * (1 + 8.0 / chi)
+        assert 12 * chi ** 9 < fw < 12 * chi ** 9 * (1 + 8.0 / chi)
+        # one placement costs half of the averaged call in the chi^9 terms
+        fl = _lib.mera_flops(_lib.MERA_OP_DESCEND, chi, chi, 0)
+        assert abs(fl / _lib.mera_flops(_lib.MERA_OP_DESCEND, chi, chi, 2) - 0.5) < 0.06
+
+
+def test_native_hamiltonian_matches_oracle(lib):
+    from oracle import mera_oracle as O
+    for g in (1.0, 0.5, 1.7):
+        st, h, c = _lib.mera_tfim_hamiltonian(g)
+        assert st == 0
+        h3 = O.tfim_three_site(g)
+        c_ref = np.linalg.eigvalsh(h3)[-1]
+        assert abs(c - c_ref) < 1e-14
+        assert np.abs(np.array(h).reshape(8, 8) - (h3 - c_ref * np.eye(8))).max() < 1e-14

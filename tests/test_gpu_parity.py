@@ -1,0 +1,169 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, element by element.
+
+Tolerances: FP64 contractions 1e-12 relative Frobenius error (the schedules
+differ from the oracle's in order of summation only); FP32 and split-bf16
+paths are checked against bounds derived from their unit roundoff
+(FP32: 2^-24 per product, K-term sums; split bf16: about 2^-16 per product).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mera_oracle as O
+from paper_1906_12030_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def ops():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_12030_amd import ops as _ops
+    return _ops
+
+
+def say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+SHAPES = [(2, 2), (2, 4), (3, 3), (4, 4), (3, 7), (4, 16), (6, 6), (8, 8)]
+PLACE = {"L": "L", "R": "R", "AVG": "AVG"}
+
+
+def _case(din, dout, seed):
+    rng = np.random.default_rng(1000 * din + dout + seed)
+    u, w = I.random_layer(rng, din, dout)
+    rho = I.random_density(rng, dout)
+    h = I.random_symmetric(rng, din)
+    return u, w, rho, h
+
+
+@pytest.mark.parametrize("din,dout", SHAPES)
+@pytest.mark.parametrize("placement", ["L", "R", "AVG"])
+def test_descend_ascend_fp64(ops, din, dout, placement):
+    u, w, rho, h = _case(din, dout, 0)
+    say(f"descend/ascend fp64 din={din} dout={dout} placement={placement}")
+    layer = ops.Layer(gpu(u), gpu(w))
+    d = host(ops.descend(layer, gpu(rho), placement, "fp64"))
+    ref = O.apply_placement(O.descend_placement, u, w, rho, placement)
+    assert rel(d, ref) < TOL["fp64"]
+    a = host(ops.ascend(layer, gpu(h), placement, "fp64"))
+    ref = O.apply_placement(O.ascend_placement, u, w, h, placement)
+    assert rel(a, ref) < TOL["fp64"]
+
+
+@pytest.mark.parametrize("din,dout", SHAPES)
+@pytest.mark.parametrize("placement", ["L", "R", "AVG"])
+def test_environments_fp64(ops, din, dout, placement):
+    u, w, rho, h = _case(din, dout, 1)
+    say(f"env fp64 din={din} dout={dout} placement={placement}")
+    layer = ops.Layer(gpu(u), gpu(w))
+    eu = host(ops.env_u(layer, gpu(h), gpu(rho), placement, "fp64"))
+    ew = host(ops.env_w(layer, gpu(h), gpu(rho), placement, "fp64"))
+    assert rel(eu, O.env_u(u, w, h, rho, placement)) < TOL["fp64"]
+    assert rel(ew, O.env_w(u, w, h, rho, placement)) < TOL["fp64"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("din,dout", [(3, 3), (4, 16), (8, 8)])
+def test_reduced_precision_paths(ops, prec, din, dout):
+    u, w, rho, h = _case(din, dout, 2)
+    say(f"{prec} din={din} dout={dout}")
+    layer = ops.Layer(gpu(u), gpu(w))
+    checks = [
+        (ops.descend(layer, gpu(rho), "AVG", prec), O.descend(u, w, rho)),
+        (ops.ascend(layer, gpu(h), "AVG", prec), O.ascend(u, w, h)),
+        (ops.env_u(layer, gpu(h), gpu(rho), "AVG", prec), O.env_u(u, w, h, rho)),
+        (ops.env_w(layer, gpu(h), gpu(rho), "AVG", prec), O.env_w(u, w, h, rho)),
+    ]
+    for g, r in checks:
+        err = rel(host(g), r)
+        say(f"  rel err {err:.3e}")
+        assert err < TOL[prec]
+
+
+def test_large_chi12_descend(ops):
+    """chi = 12: several 128-wide tiles in every GEMM, ragged tails (12^2 = 144)."""
+    u, w, rho, h = _case(12, 12, 3)
+    say("descend fp64 chi=12")
+    layer = ops.Layer(gpu(u), gpu(w))
+    d = host(ops.descend(layer, gpu(rho), "AVG", "fp64"))
+    assert rel(d, O.descend(u, w, rho)) < TOL["fp64"]
+    a = host(ops.ascend(layer, gpu(h), "AVG", "fp64"))
+    assert rel(a, O.ascend(u, w, h)) < TOL["fp64"]
+
+
+@pytest.mark.parametrize("rows,cols", [(4, 4), (16, 4), (16, 16), (64, 8), (81, 81), (256, 16), (576, 24)])
+def test_polar_update(ops, rows, cols):
+    rng = np.random.default_rng(rows + 7 * cols)
+    y = rng.standard_normal((rows, cols))
+    say(f"polar rows={rows} cols={cols}")
+    out, iters, st = ops.polar_update(gpu(y), rows, cols)
+    got = host(out)
+    ref, s = O.polar_update_matrix(y)
+    # the polar factor's condition number is about 1/sigma_min (relative)
+    cond = s[0] / s[-1]
+    assert st == 0
+    assert np.abs(got - ref).max() < 1e-13 * cond * max(1.0, np.sqrt(cols))
+    assert np.abs(got.T @ got - np.eye(cols)).max() < 1e-13
+
+
+def test_polar_rejects_rank_deficient(ops):
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal((16, 4)) @ np.diag([1.0, 1.0, 1.0, 0.0])
+    out, iters, st = ops.polar_update(gpu(y), 16, 4, check=False)
+    assert st == 5  # MERA_ENUMERIC
+    z = np.zeros((9, 3))
+    out, iters, st = ops.polar_update(gpu(z), 9, 3, check=False)
+    assert st == 5
+
+
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_fixed_point(ops, d):
+    rng = np.random.default_rng(40 + d)
+    u, w = I.random_layer(rng, d, d)
+    say(f"fixed point d={d}")
+    rho0 = O.identity_density(d)
+    ref = O.fixed_point_rho(u, w, rho0, 25)
+    layer = ops.Layer(gpu(u), gpu(w))
+    r = gpu(rho0)
+    _, res = ops.fixed_point_rho(layer, r, 25, "fp64", want_residual=True)
+    assert rel(host(r), ref) < 1e-12
+    prev = O.fixed_point_rho(u, w, rho0, 24)
+    want = np.linalg.norm(ref - prev) / np.linalg.norm(ref)
+    assert abs(host(res)[0] - want) < 1e-10 + 1e-6 * want
+
+
+def test_energy_and_hamiltonian(ops):
+    h_gpu, c = ops.tfim_hamiltonian(1.0)
+    h_ref, c_ref = O.shifted_hamiltonian(1.0)
+    assert abs(c - c_ref) < 1e-14
+    assert np.abs(host(h_gpu) - h_ref).max() < 1e-14
+    rng = np.random.default_rng(3)
+    for n in (8, 27, 64, 1000):
+        a = rng.standard_normal((n, n))
+        b = rng.standard_normal((n, n))
+        e = host(ops.energy(gpu(a), gpu(b)))[0]
+        assert abs(e - np.trace(a @ b)) < 1e-12 * n * n
+        # bitwise reproducible
+        assert host(ops.energy(gpu(a), gpu(b)))[0] == e
