@@ -1,0 +1,203 @@
+"""Benchmark: scale-invariant binary MERA sweep for the critical Ising chain at chi = 24.
+
+One step = one optimisation sweep (ascend h, scale-invariant u/w updates, 30
+power iterations for rho*, transitional-layer updates, energy) on seeded
+synthetic tensors, with the contractions in split-bf16 ("mixed") precision and
+polar updates, fixed-point renormalisation and energy in FP64.  The same sweep
+in plain FP64 is timed beside it for the mixed-vs-FP64 ratio.
+
+Prints one JSON line (see the keys below).  Runs on one GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published dense peaks, TFLOP/s
+    "fp64": 78.6,
+    "fp32": 157.3,
+    "bf16": 2516.6,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--chi", type=int, default=24)
+    ap.add_argument("--layers", type=int, default=3)
+    ap.add_argument("--iters", type=int, default=30)
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "fp64"])
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warmup + timed sweeps only (for external profilers)")
+    return ap.parse_args()
+
+
+def cpu_baseline(chi: int, seed: int) -> dict:
+    """The FP64 oracle on a bounded sample of the same workload, on the host cores."""
+    import numpy as np
+
+    from oracle import mera_oracle as O
+    from paper_1906_12030_amd import inputs as I
+
+    rng = np.random.default_rng(seed)
+    u, w = I.random_layer(rng, chi, chi)
+    g = rng.standard_normal((chi ** 3, 64))
+    rho = (g @ g.T)
+    rho /= np.trace(rho)
+    rho = rho.reshape((chi,) * 6)
+    t0 = time.perf_counter()
+    flops = 0.0
+    O.descend_placement_slice(u, w, rho, "L", 0)
+    dt = time.perf_counter() - t0
+    # the work of that sample in the GPU schedule's own flop count (1/chi of a left-window descend)
+    from paper_1906_12030_amd import ops
+    flops = ops.flops("descend", chi, chi, "L") / chi
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(d.get("num_threads", 1)) for d in threadpool_info()) if threadpool_info() else os.cpu_count()
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "seconds": dt,
+            "sample": f"oracle D_L at chi={chi} with the first fine leg fixed to one value "
+                      f"(1/{chi} of a left-window descend, {flops:.3e} flop in the GPU schedule's count)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of this build",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_1906_12030_amd import _lib, ops, sweep
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    chi, T = args.chi, args.layers
+    m = sweep.GpuMera.seeded(chi, T, args.seed)
+    h1, shift = ops.tfim_hamiltonian(1.0)
+    prec = args.precision
+    flops = sweep.sweep_flops(sweep.layer_dims(m), args.iters)
+    print(f"# chi={chi} T={T} dims={sweep.layer_dims(m)} precision={prec} sweep flops={flops['total']:.3e}",
+          file=sys.stderr, flush=True)
+    sweep.initial_fixed_point(m, args.iters, prec)
+    torch.cuda.synchronize()
+    for k in range(args.warmup):
+        sweep.sweep(m, h1, shift, args.iters, prec)
+        torch.cuda.synchronize()
+        print(f"# warmup sweep {k} done", file=sys.stderr, flush=True)
+    start_state = m.state_dict()
+
+    # ---- timed mixed-precision sweeps (per-launch events recorded by the library) ----
+    _lib.mera_profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_mixed = None
+    for k in range(args.steps):
+        e, c = sweep.sweep(m, h1, shift, args.iters, prec)
+        e_mixed = e
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / args.steps
+    st, recs = _lib.mera_profile_end()
+    e_mixed = float(e_mixed.item()) + shift
+    print(f"# mixed sweeps: {t_mixed:.3f} s/sweep, e = {e_mixed:.12f}", file=sys.stderr, flush=True)
+    if args.profile_only:
+        return
+
+    # dominant kernel: the chi^9 contraction launches (four per descend / ascend call)
+    big = [r for r in recs if r[2] >= 0.5 * max(x[2] for x in recs)]
+    big_f = sum(r[2] for r in big)
+    big_ms = sum(r[3] for r in big)
+    all_ms = sum(r[3] for r in recs)
+    all_f = sum(r[2] for r in recs)
+
+    # ---- plain FP64 sweep(s) from the same starting state, for the ratio ----
+    t_fp64 = None
+    e_fp64 = None
+    if args.fp64_steps > 0:
+        m64 = sweep.GpuMera(start_state["layers"], start_state["si"], start_state["rho_star"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.fp64_steps):
+            e, c = sweep.sweep(m64, h1, shift, args.iters, "fp64")
+            if k == 0:
+                e_fp64_first = float(e.item()) + shift
+        torch.cuda.synchronize()
+        t_fp64 = (time.perf_counter() - t0) / args.fp64_steps
+        e_fp64 = e_fp64_first
+        print(f"# fp64 sweep: {t_fp64:.3f} s/sweep, e = {e_fp64:.12f}", file=sys.stderr, flush=True)
+        del m64
+
+    # ---- energy evaluation at the final tensors: mixed pipeline vs FP64 pipeline ----
+    def eval_energy(precision):
+        mm = sweep.GpuMera([(u.clone(), w.clone()) for u, w in m.layers], (m.si[0].clone(), m.si[1].clone()),
+                           m.rho_star.clone())
+        sweep.initial_fixed_point(mm, args.iters, precision)
+        return sweep.energy(mm, h1, shift, precision)
+
+    e_eval_mixed = eval_energy(prec)
+    e_eval_fp64 = eval_energy("fp64")
+    print(f"# energy at final tensors: mixed {e_eval_mixed:.15f}  fp64 {e_eval_fp64:.15f}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if args.cpu_baseline:
+        cpu = cpu_baseline(chi, args.seed)
+        print(f"# cpu baseline: {cpu}", file=sys.stderr, flush=True)
+
+    value = flops["total"] / t_mixed / 1e12
+    roof_peak = PEAK["bf16"] / 3.0 if prec == "bf16x3" else PEAK[prec]
+    achieved = big_f / (big_ms / 1e3) / 1e12
+    out = {
+        "metric": "MERA sweep s & env-contraction TFLOP/s at chi=24, mixed vs FP64, |dE|<=1e-9",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_mixed, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic (seeded QR-of-Gaussian MERA tensors, exact TFIM h=1)",
+        "config": {"workload": f"scale-invariant binary MERA sweep, critical TFIM, chi={chi}, "
+                               f"{T} transitional layers ({'-'.join(str(a) for a, _ in sweep.layer_dims(m)[:-1])}-{chi}) "
+                               f"+ SI layer, {args.iters} power iterations, seed {args.seed}",
+                   "chi": chi, "transitional_layers": T, "power_iterations": args.iters,
+                   "contraction_precision": prec},
+        "sweep_s_mixed": round(t_mixed, 4),
+        "sweep_s_fp64": round(t_fp64, 4) if t_fp64 else None,
+        "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3) if t_fp64 else None,
+        "sweep_flops": flops,
+        "contraction_tflops_all_launches": round(all_f / (all_ms / 1e3) / 1e12, 3),
+        "energy_after_mixed_sweeps": e_mixed,
+        "energy_after_one_fp64_sweep_from_same_start": e_fp64,
+        "energy_eval_final_tensors_mixed": e_eval_mixed,
+        "energy_eval_final_tensors_fp64": e_eval_fp64,
+        "dE_eval": abs(e_eval_mixed - e_eval_fp64),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(roof_peak, 1),
+                     "unit": "TFLOP/s", "frac": round(achieved / roof_peak, 4), "traffic": None,
+                     "kernel": f"chi^9 contraction launches ({prec}), {len(big)} launches, "
+                               f"{big_f / len(big):.3e} flop each, avg {big_ms / len(big):.3f} ms",
+                     "note": "split-bf16 peak = bf16 dense MFMA peak / 3 (three bf16 products per useful multiply-add)"
+                     if prec == "bf16x3" else ""},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

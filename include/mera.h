@@ -151,6 +151,21 @@ int mera_tfim_hamiltonian(double field, double* h_host /* 64 doubles */, double*
  * arguments.  Pure host function. */
 size_t mera_workspace_bytes(int op, int32_t din, int32_t dout, int precision, int placement);
 
+/* Per-launch timing of the contraction kernels, for profiling and roofline
+ * accounting.  mera_profile_begin() starts recording (on this thread) a pair
+ * of HIP events around every contraction launch; mera_profile_end() waits for
+ * the recorded events, copies up to max_entries records into out (host
+ * memory), stores their count in *n_out and stops recording.  Recording adds
+ * two event records per launch and does not change any result. */
+typedef struct {
+  char step[48];    /* "la,lb->lc" leg labels of the contraction */
+  int32_t arith;    /* mera_precision of the launch */
+  double flops;     /* 2*M*N*K of the launch */
+  double ms;        /* device time between the two events */
+} mera_profile_entry;
+int mera_profile_begin(void);
+int mera_profile_end(mera_profile_entry* out, int32_t max_entries, int32_t* n_out);
+
 /* Static text for a status code. */
 const char* mera_strerror(int status);
 

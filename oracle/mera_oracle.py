@@ -254,6 +254,19 @@ def descend_placement(u, w, rho, placement):
     return _einsum(subs + [coarse], ops + [rho], fine)
 
 
+def descend_placement_slice(u, w, rho, placement, index):
+    """D_P(rho) with its first fine (ket) leg fixed to `index`: the same network,
+    with the ket disentangler that carries that leg sliced (a 1/d share of D_P)."""
+    subs, ops, coarse, fine = _network_operands(u, w, placement)
+    # the ket uL carries f1 (left window's first leg) at position 0 and f2 (right
+    # window's first leg) at position 1
+    pos = 0 if placement == "L" else 1
+    lbl = subs[0]
+    subs = [lbl[:pos] + lbl[pos + 1:]] + subs[1:]
+    ops = [np.take(ops[0], index, axis=pos)] + ops[1:]
+    return _einsum(subs + [coarse], ops + [rho], fine[1:])
+
+
 def ascend_placement(u, w, op, placement):
     """A_P(op): coarse three-site operator from the fine operator op on window P."""
     subs, ops, coarse, fine = _network_operands(u, w, placement)

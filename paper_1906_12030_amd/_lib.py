@@ -21,13 +21,18 @@ MERA_FP64, MERA_FP32, MERA_BF16X3 = 0, 1, 2
 EXPORTED = (
     "mera_ascend", "mera_descend", "mera_env_u", "mera_env_w", "mera_polar_update",
     "mera_fixed_point_rho", "mera_energy", "mera_tfim_hamiltonian", "mera_workspace_bytes",
-    "mera_strerror", "mera_last_error", "mera_flops",
+    "mera_strerror", "mera_last_error", "mera_flops", "mera_profile_begin", "mera_profile_end",
 )
 
 
 class MeraLayer(ctypes.Structure):
     _fields_ = [("din", ctypes.c_int32), ("dout", ctypes.c_int32),
                 ("u_d", ctypes.c_void_p), ("w_d", ctypes.c_void_p)]
+
+
+class MeraProfileEntry(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_char * 48), ("arith", ctypes.c_int32),
+                ("flops", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
 class MeraError(RuntimeError):
@@ -65,6 +70,10 @@ def load() -> ctypes.CDLL:
     lib.mera_strerror.restype = ctypes.c_char_p
     lib.mera_last_error.argtypes = []
     lib.mera_last_error.restype = ctypes.c_char_p
+    lib.mera_profile_begin.argtypes = []
+    lib.mera_profile_begin.restype = ctypes.c_int
+    lib.mera_profile_end.argtypes = [ctypes.POINTER(MeraProfileEntry), i32, ctypes.POINTER(i32)]
+    lib.mera_profile_end.restype = ctypes.c_int
     for name in ("mera_ascend", "mera_descend", "mera_env_u", "mera_env_w", "mera_polar_update",
                  "mera_fixed_point_rho", "mera_energy", "mera_tfim_hamiltonian"):
         getattr(lib, name).restype = ctypes.c_int
@@ -123,3 +132,15 @@ def mera_workspace_bytes(op, din, dout, precision, placement):
 
 def mera_flops(op, din, dout, placement):
     return float(load().mera_flops(op, din, dout, placement))
+
+
+def mera_profile_begin():
+    return load().mera_profile_begin()
+
+
+def mera_profile_end(max_entries=200000):
+    buf = (MeraProfileEntry * max_entries)()
+    n = ctypes.c_int32(0)
+    st = load().mera_profile_end(buf, max_entries, ctypes.byref(n))
+    return st, [(buf[i].step.decode(), int(buf[i].arith), float(buf[i].flops), float(buf[i].ms))
+                for i in range(n.value)]

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -59,47 +60,21 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T, int V>
-struct VecLoad;
-template <typename T>
-struct VecLoad<T, 1> {
-  static __device__ __forceinline__ void load(const T* p, T* out) { out[0] = *p; }
-};
-template <>
-struct VecLoad<double, 2> {
-  static __device__ __forceinline__ void load(const double* p, double* out) {
-    typedef double v2 __attribute__((ext_vector_type(2)));
-    v2 v = *reinterpret_cast<const v2*>(p);
-    out[0] = v.x;
-    out[1] = v.y;
-  }
-};
-template <>
-struct VecLoad<float, 4> {
-  static __device__ __forceinline__ void load(const float* p, float* out) {
-    typedef float v4 __attribute__((ext_vector_type(4)));
-    v4 v = *reinterpret_cast<const v4*>(p);
-    out[0] = v.x;
-    out[1] = v.y;
-    out[2] = v.z;
-    out[3] = v.w;
-  }
-};
-
-constexpr int kThreads = 256;
 constexpr int kBM = 128;
 constexpr int kBN = 128;
 constexpr int kBK = 16;
 constexpr int kPad = 4;
 
-template <typename T, typename TC, bool A_KC, int VA, bool B_NC, int VB>
+template <typename T, typename TC, bool A_KC, int VA, bool B_NC, int VB, bool KAL>
 __global__ __launch_bounds__(kThreads) void tc_mfma_kernel(TcArgs p) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T As[2][kBK][kBM + kPad];
-  __shared__ T Bs[2][kBK][kBN + kPad];
+  constexpr int kStage = kBK * (kBM + kPad);  // elements of one operand stage
+  __shared__ __attribute__((aligned(16))) char smem[4 * kStage * sizeof(T)];
+  T (*As)[kBK][kBM + kPad] = reinterpret_cast<T (*)[kBK][kBM + kPad]>(smem);
+  T (*Bs)[kBK][kBN + kPad] = reinterpret_cast<T (*)[kBK][kBN + kPad]>(smem + 2 * kStage * sizeof(T));
 
-  int tm, tn;
-  if (!tile_of_block(p, tm, tn)) return;
+  int tm, tn, split;
+  if (!tile_of_block(p, tm, tn, split)) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -107,132 +82,35 @@ __global__ __launch_bounds__(kThreads) void tc_mfma_kernel(TcArgs p) {
   const int wn = (wave & 1) * 64;
   const uint32_t m0 = (uint32_t)tm * kBM;
   const uint32_t n0 = (uint32_t)tn * kBN;
+  const uint32_t kbeg = (uint32_t)split * (uint32_t)p.kchunk;
+  const uint32_t kend = min((uint32_t)p.K, kbeg + (uint32_t)p.kchunk);
   const T* __restrict__ A = static_cast<const T*>(p.a);
   const T* __restrict__ B = static_cast<const T*>(p.b);
 
-  // ---- loader geometry for A ----
-  // A_KC: each thread loads VA consecutive k of one row; else VA consecutive rows at one k.
-  constexpr int A_TPR = A_KC ? kBK / VA : kBM / VA;          // threads per row (KC) or per k-line
-  constexpr int A_RPP = kThreads / A_TPR;                     // rows (KC) or k-lines per pass
-  constexpr int A_NP = A_KC ? kBM / A_RPP : kBK / A_RPP;      // passes
-  constexpr int B_TPR = B_NC ? kBN / VB : kBK / VB;
-  constexpr int B_RPP = kThreads / B_TPR;
-  constexpr int B_NP = B_NC ? kBK / B_RPP : kBN / B_RPP;
-  static_assert(A_NP >= 1 && B_NP >= 1, "tile geometry");
-
-  const int a_line = tid / A_TPR;
-  const int a_vec = (tid % A_TPR) * VA;
-  const int b_line = tid / B_TPR;
-  const int b_vec = (tid % B_TPR) * VB;
-
-  int64_t a_off[A_KC ? A_NP : 1];
-  bool a_ok[A_KC ? A_NP : 1];
-  if (A_KC) {
-#pragma unroll
-    for (int i = 0; i < A_NP; ++i) {
-      const uint32_t m = m0 + a_line + i * A_RPP;
-      a_ok[i] = m < (uint32_t)p.M;
-      a_off[i] = a_ok[i] ? goff<false>(p.gm, m) : 0;
-    }
-  } else {
-    const uint32_t m = m0 + a_vec;
-    a_ok[0] = m < (uint32_t)p.M;
-    a_off[0] = a_ok[0] ? goff<false>(p.gm, m) : 0;
-  }
-  int64_t b_off[B_NC ? 1 : B_NP];
-  bool b_ok[B_NC ? 1 : B_NP];
-  if (B_NC) {
-    const uint32_t n = n0 + b_vec;
-    b_ok[0] = n < (uint32_t)p.N;
-    b_off[0] = b_ok[0] ? goff<false>(p.gn, n) : 0;
-  } else {
-#pragma unroll
-    for (int i = 0; i < B_NP; ++i) {
-      const uint32_t n = n0 + b_line + i * B_RPP;
-      b_ok[i] = n < (uint32_t)p.N;
-      b_off[i] = b_ok[i] ? goff<false>(p.gn, n) : 0;
-    }
-  }
-
-  T ra[A_NP][VA];
-  T rb[B_NP][VB];
-
-  auto load_tiles = [&](uint32_t k0) {
-    if (A_KC) {
-      const uint32_t k = k0 + a_vec;
-      const bool kok = k < (uint32_t)p.K;
-      const int64_t ko = kok ? goff<false>(p.gk, k) : 0;
-#pragma unroll
-      for (int i = 0; i < A_NP; ++i) {
-        if (kok && a_ok[i]) {
-          VecLoad<T, VA>::load(A + a_off[i] + ko, ra[i]);
-        } else {
-#pragma unroll
-          for (int v = 0; v < VA; ++v) ra[i][v] = T(0);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < A_NP; ++i) {
-        const uint32_t k = k0 + a_line + i * A_RPP;
-        if (k < (uint32_t)p.K && a_ok[0]) {
-          VecLoad<T, VA>::load(A + a_off[0] + goff<false>(p.gk, k), ra[i]);
-        } else {
-#pragma unroll
-          for (int v = 0; v < VA; ++v) ra[i][v] = T(0);
-        }
-      }
-    }
-    if (B_NC) {
-#pragma unroll
-      for (int i = 0; i < B_NP; ++i) {
-        const uint32_t k = k0 + b_line + i * B_RPP;
-        if (k < (uint32_t)p.K && b_ok[0]) {
-          VecLoad<T, VB>::load(B + b_off[0] + goff<true>(p.gk, k), rb[i]);
-        } else {
-#pragma unroll
-          for (int v = 0; v < VB; ++v) rb[i][v] = T(0);
-        }
-      }
-    } else {
-      const uint32_t k = k0 + b_vec;
-      const bool kok = k < (uint32_t)p.K;
-      const int64_t ko = kok ? goff<true>(p.gk, k) : 0;
-#pragma unroll
-      for (int i = 0; i < B_NP; ++i) {
-        if (kok && b_ok[i]) {
-          VecLoad<T, VB>::load(B + b_off[i] + ko, rb[i]);
-        } else {
-#pragma unroll
-          for (int v = 0; v < VB; ++v) rb[i][v] = T(0);
-        }
-      }
-    }
-  };
+  TileLoad<T, kBM, kBK, A_KC, VA, KAL, false> la;
+  TileLoad<T, kBN, kBK, !B_NC, VB, KAL, true> lb;
+  la.init(p.gm, p.gk, m0, (uint32_t)p.M);
+  lb.init(p.gn, p.gk, n0, (uint32_t)p.N);
 
   auto store_tiles = [&](int buf) {
-    if (A_KC) {
 #pragma unroll
-      for (int i = 0; i < A_NP; ++i)
+    for (int i = 0; i < la.NP; ++i)
 #pragma unroll
-        for (int v = 0; v < VA; ++v) As[buf][a_vec + v][a_line + i * A_RPP] = ra[i][v];
-    } else {
+      for (int v = 0; v < VA; ++v) {
+        if (A_KC)
+          As[buf][la.vec + v][la.line + i * la.LPP] = la.r[i][v];
+        else
+          As[buf][la.line + i * la.LPP][la.vec + v] = la.r[i][v];
+      }
 #pragma unroll
-      for (int i = 0; i < A_NP; ++i)
+    for (int i = 0; i < lb.NP; ++i)
 #pragma unroll
-        for (int v = 0; v < VA; ++v) As[buf][a_line + i * A_RPP][a_vec + v] = ra[i][v];
-    }
-    if (B_NC) {
-#pragma unroll
-      for (int i = 0; i < B_NP; ++i)
-#pragma unroll
-        for (int v = 0; v < VB; ++v) Bs[buf][b_line + i * B_RPP][b_vec + v] = rb[i][v];
-    } else {
-#pragma unroll
-      for (int i = 0; i < B_NP; ++i)
-#pragma unroll
-        for (int v = 0; v < VB; ++v) Bs[buf][b_vec + v][b_line + i * B_RPP] = rb[i][v];
-    }
+      for (int v = 0; v < VB; ++v) {
+        if (B_NC)
+          Bs[buf][lb.line + i * lb.LPP][lb.vec + v] = lb.r[i][v];
+        else
+          Bs[buf][lb.vec + v][lb.line + i * lb.LPP] = lb.r[i][v];
+      }
   };
 
   acc_t acc[4][4];
@@ -241,15 +119,26 @@ __global__ __launch_bounds__(kThreads) void tc_mfma_kernel(TcArgs p) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  const int nk = (p.K + kBK - 1) / kBK;
-  load_tiles(0);
+  const int nk = (int)((kend - kbeg + kBK - 1) / kBK);
+  KWalk<kBK> kw;
+  if constexpr (KAL) kw.init(p.gk, kbeg);
+  // k-tile fetch: carry walk for k-aligned tiles, leg decomposition otherwise
+  auto fetch = [&](int kt) {
+    if constexpr (KAL) {
+      if (kt > 0) kw.next(p.gk);
+      la.load_at(A, kw.oa);
+      lb.load_at(B, kw.ob);
+    } else {
+      la.load(A, p.gk, kbeg + (uint32_t)kt * kBK, kend);
+      lb.load(B, p.gk, kbeg + (uint32_t)kt * kBK, kend);
+    }
+  };
+  fetch(0);
   store_tiles(0);
   __syncthreads();
   const int lr = lane & 15;
   const int lk = lane >> 4;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) load_tiles((uint32_t)(kt + 1) * kBK);
+  auto compute = [&](int cur) {
 #pragma unroll
     for (int ks = 0; ks < kBK / 4; ++ks) {
       T a[4], b[4];
@@ -262,36 +151,34 @@ __global__ __launch_bounds__(kThreads) void tc_mfma_kernel(TcArgs p) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::mac(a[i], b[j], acc[i][j]);
     }
-    if (kt + 1 < nk) store_tiles(cur ^ 1);
+  };
+  // steady state without branches: prefetch k-tile kt+1 while multiplying tile kt
+  for (int kt = 0; kt + 1 < nk; ++kt) {
+    const int cur = kt & 1;
+    fetch(kt + 1);
+    compute(cur);
+    store_tiles(cur ^ 1);
     __syncthreads();
   }
+  compute((nk - 1) & 1);
+  __syncthreads();
+  write_tile<T, TC>(p, acc, m0, n0, split, smem,
+                    [](int ln, int r) { return Mfma<T>::row(ln, r); });
+}
 
-  // ---- epilogue: scatter with separable offsets ----
-  TC* __restrict__ C = static_cast<TC*>(p.c);
-  int64_t coff[4];
-  bool cok[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint32_t n = n0 + wn + j * 16 + lr;
-    cok[j] = n < (uint32_t)p.N;
-    coff[j] = cok[j] ? goff<true>(p.gn, n) : 0;
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t m = m0 + wm + i * 16 + Mfma<T>::row(lane, r);
-      if (m >= (uint32_t)p.M) continue;
-      const int64_t ro = goff<true>(p.gm, m);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (!cok[j]) continue;
-        TC* dst = C + ro + coff[j];
-        double v = p.alpha * (double)acc[i][j][r];
-        if (p.beta != 0.0) v += p.beta * (double)(*dst);
-        *dst = (TC)v;
-      }
-    }
+// C = alpha * sum over splits of the partial sums + beta * C
+template <typename TC>
+__global__ __launch_bounds__(256) void tc_splitk_reduce(TcArgs p) {
+  const int64_t mn = (int64_t)p.M * p.N;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < mn;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < p.splits; ++c) s += p.part[c * mn + t];
+    const uint32_t m = (uint32_t)(t / p.N), n = (uint32_t)(t - (int64_t)m * p.N);
+    TC* dst = static_cast<TC*>(p.c) + goff<true>(p.gm, m) + goff<true>(p.gn, n);
+    double y = p.alpha * s;
+    if (p.beta != 0.0) y += p.beta * (double)(*dst);
+    *dst = (TC)y;
   }
 }
 
@@ -357,43 +244,46 @@ bool build_group(const std::string& legs, const std::string& lx, const std::stri
   return total < (int64_t(1) << 31);
 }
 
-template <typename T, typename TC, bool AKC, int VA, bool BNC, int VB>
+template <typename T, typename TC, bool AKC, int VA, bool BNC, int VB, bool KAL>
 hipError_t launch_one(const TcArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((tc_mfma_kernel<T, TC, AKC, VA, BNC, VB>), dim3(blocks), dim3(kThreads), 0, s,
-                     a);
+  hipLaunchKernelGGL((tc_mfma_kernel<T, TC, AKC, VA, BNC, VB, KAL>), dim3(blocks), dim3(kThreads),
+                     0, s, a);
   return hipGetLastError();
 }
 
+// Instantiated variants: k-aligned tiles with or without vector loads on each
+// operand; unaligned tiles with element loads only.
 template <typename T, typename TC>
-hipError_t dispatch(const TcArgs& a, int blocks, bool akc, bool va, bool bnc, bool vb,
+hipError_t dispatch(const TcArgs& a, int blocks, bool akc, bool va, bool bnc, bool vb, bool kal,
                     hipStream_t s) {
   constexpr int W = 16 / sizeof(T);
-  if (akc) {
-    if (bnc) {
-      if (va)
-        return vb ? launch_one<T, TC, true, W, true, W>(a, blocks, s)
-                  : launch_one<T, TC, true, W, true, 1>(a, blocks, s);
-      return vb ? launch_one<T, TC, true, 1, true, W>(a, blocks, s)
-                : launch_one<T, TC, true, 1, true, 1>(a, blocks, s);
-    }
-    if (va)
-      return vb ? launch_one<T, TC, true, W, false, W>(a, blocks, s)
-                : launch_one<T, TC, true, W, false, 1>(a, blocks, s);
-    return vb ? launch_one<T, TC, true, 1, false, W>(a, blocks, s)
-              : launch_one<T, TC, true, 1, false, 1>(a, blocks, s);
+  if (!kal) {
+    if (akc) return bnc ? launch_one<T, TC, true, 1, true, 1, false>(a, blocks, s)
+                        : launch_one<T, TC, true, 1, false, 1, false>(a, blocks, s);
+    return bnc ? launch_one<T, TC, false, 1, true, 1, false>(a, blocks, s)
+               : launch_one<T, TC, false, 1, false, 1, false>(a, blocks, s);
   }
-  if (bnc) {
-    if (va)
-      return vb ? launch_one<T, TC, false, W, true, W>(a, blocks, s)
-                : launch_one<T, TC, false, W, true, 1>(a, blocks, s);
-    return vb ? launch_one<T, TC, false, 1, true, W>(a, blocks, s)
-              : launch_one<T, TC, false, 1, true, 1>(a, blocks, s);
-  }
-  if (va)
-    return vb ? launch_one<T, TC, false, W, false, W>(a, blocks, s)
-              : launch_one<T, TC, false, W, false, 1>(a, blocks, s);
-  return vb ? launch_one<T, TC, false, 1, false, W>(a, blocks, s)
-            : launch_one<T, TC, false, 1, false, 1>(a, blocks, s);
+#define MERA_TC_CASE(AK, AV, BN, BV)                                              \
+  if (akc == AK && (va ? W : 1) == AV && bnc == BN && (vb ? W : 1) == BV)        \
+    return launch_one<T, TC, AK, AV, BN, BV, true>(a, blocks, s);
+  MERA_TC_CASE(true, W, true, W)
+  MERA_TC_CASE(true, W, true, 1)
+  MERA_TC_CASE(true, 1, true, W)
+  MERA_TC_CASE(true, 1, true, 1)
+  MERA_TC_CASE(true, W, false, W)
+  MERA_TC_CASE(true, W, false, 1)
+  MERA_TC_CASE(true, 1, false, W)
+  MERA_TC_CASE(true, 1, false, 1)
+  MERA_TC_CASE(false, W, true, W)
+  MERA_TC_CASE(false, W, true, 1)
+  MERA_TC_CASE(false, 1, true, W)
+  MERA_TC_CASE(false, 1, true, 1)
+  MERA_TC_CASE(false, W, false, W)
+  MERA_TC_CASE(false, W, false, 1)
+  MERA_TC_CASE(false, 1, false, W)
+  MERA_TC_CASE(false, 1, false, 1)
+#undef MERA_TC_CASE
+  return hipErrorInvalidValue;
 }
 
 // Vector width usable along the unit-stride leg `inner` of operand `lab`:
@@ -420,7 +310,8 @@ double contract_flops(const LabelDims& dims, const char* la_, const char* lb_, c
 
 hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* la_, const void* B,
                     const char* lb_, void* C, const char* lc_, bool c_f64, double alpha,
-                    double beta, hipStream_t stream, double* flops) {
+                    double beta, hipStream_t stream, double* flops, double* scratch,
+                    size_t scratch_elems) {
   std::string la(la_), lb(lb_), lc(lc_);
   // C's innermost leg must come from "B" so that stores run along n.
   if (!lc.empty() && contains(la, lc.back()) && !contains(lb, lc.back())) {
@@ -488,21 +379,67 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
                  : (vec_ok(lb, lb.back(), dims, W) && args.gk.size[args.gk.nd - 1] % W == 0);
   if (reinterpret_cast<uintptr_t>(A) % 16) va = false;
   if (reinterpret_cast<uintptr_t>(B) % 16) vb = false;
+  // k-aligned tiles: the innermost k leg's extent is a multiple of the k-tile
+  const int bk = (ar == Arith::B3) ? 32 : 16;
+  const bool kal = args.gk.size[args.gk.nd - 1] % bk == 0;
+  if (!kal) va = vb = false;
   args.tiles_m = (int32_t)((M + kBM - 1) / kBM);
   args.tiles_n = (int32_t)((N + kBN - 1) / kBN);
-  const int64_t total = (int64_t)args.tiles_m * args.tiles_n;
-  args.per_xcd = (int32_t)((total + 7) / 8);
+  const int64_t tiles = (int64_t)args.tiles_m * args.tiles_n;
+  // Split k when the output has too few tiles to fill the GPU (two resident
+  // workgroups on each of the 256 CUs): pick the split count that best fills
+  // whole waves of workgroups, with at least 8 k-tiles per split.
+  int splits = 1;
+  int64_t kchunk = ((K + bk - 1) / bk) * bk;
+  if (scratch && scratch_elems > 0) {
+    constexpr double kSlots = 512.0;
+    auto fill = [&](int64_t n) { return (double)n / (std::ceil((double)n / kSlots) * kSlots); };
+    double best = fill(tiles);
+    for (int s = 2; s <= 16; ++s) {
+      const int64_t kc = ((K + s - 1) / s + bk - 1) / bk * bk;
+      const int64_t se = (K + kc - 1) / kc;
+      if (kc < 8 * bk || se * M * N > (int64_t)scratch_elems) break;
+      const double f = fill(tiles * se);
+      if (f > best + 0.05) {
+        best = f;
+        splits = (int)se;
+        kchunk = kc;
+      }
+    }
+  }
+  args.splits = splits;
+  args.kchunk = (int32_t)kchunk;
+  args.part = splits > 1 ? scratch : nullptr;
+  // 64-wide column spans of the tile are contiguous in the output
+  if (splits > 1)
+    args.cvec = (N % 64 == 0) ? 1 : 0;
+  else
+    args.cvec = (args.gn.sy[args.gn.nd - 1] == 1 && args.gn.size[args.gn.nd - 1] % 64 == 0 &&
+                 reinterpret_cast<uintptr_t>(C) % 16 == 0)
+                    ? 1
+                    : 0;
+  args.per_xcd = (int32_t)((tiles * splits + 7) / 8);
   args.group_m = 8;
   const int blocks = args.per_xcd * 8;
+  const bool c64 = c_f64 || splits > 1;  // partial sums are kept in double
+  hipError_t e;
   if (ar == Arith::F64) {
     if (!c_f64) return hipErrorInvalidValue;
-    return dispatch<double, double>(args, blocks, A_KC, va, B_NC, vb, stream);
+    e = dispatch<double, double>(args, blocks, A_KC, va, B_NC, vb, kal, stream);
+  } else if (ar == Arith::F32) {
+    e = c64 ? dispatch<float, double>(args, blocks, A_KC, va, B_NC, vb, kal, stream)
+            : dispatch<float, float>(args, blocks, A_KC, va, B_NC, vb, kal, stream);
+  } else {
+    e = launch_contract_b3(args, A_KC, va, B_NC, vb, kal, c64, stream);
   }
-  if (ar == Arith::F32) {
-    return c_f64 ? dispatch<float, double>(args, blocks, A_KC, va, B_NC, vb, stream)
-                 : dispatch<float, float>(args, blocks, A_KC, va, B_NC, vb, stream);
-  }
-  return launch_contract_b3(args, A_KC, va, B_NC, vb, c_f64, stream);
+  if (e != hipSuccess || splits == 1) return e;
+  const int64_t mn = M * N;
+  const int grid = (int)std::min<int64_t>((mn + 255) / 256, 8192);
+  if (c_f64)
+    hipLaunchKernelGGL(tc_splitk_reduce<double>, dim3(grid), dim3(256), 0, stream, args);
+  else
+    hipLaunchKernelGGL(tc_splitk_reduce<float>, dim3(grid), dim3(256), 0, stream, args);
+  return hipGetLastError();
 }
 
 }  // namespace mera

@@ -33,10 +33,14 @@ struct LabelDims {
 // shared by A and B and absent from C are summed; labels of C come from exactly
 // one of A and B.  A and B hold double for F64 and float otherwise; C holds
 // double when c_f64 and float otherwise.  Returns hipSuccess or the launch
-// error.  `flops` (nullable) is increased by 2*M*N*K.
+// error.  `flops` (nullable) is increased by 2*M*N*K.  `scratch` (device,
+// nullable) of scratch_elems doubles lets the engine split long k ranges over
+// several workgroups (partial sums reduced in a fixed order) when the output
+// alone has too few tiles to fill the GPU.
 hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* la, const void* B,
                     const char* lb, void* C, const char* lc, bool c_f64, double alpha, double beta,
-                    hipStream_t stream, double* flops = nullptr);
+                    hipStream_t stream, double* flops = nullptr, double* scratch = nullptr,
+                    size_t scratch_elems = 0);
 
 // Flop count of the same contraction without launching anything.
 double contract_flops(const LabelDims& dims, const char* la, const char* lb, const char* lc);

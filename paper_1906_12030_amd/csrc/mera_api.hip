@@ -42,6 +42,15 @@ thread_local std::string g_last_error;
 
 void set_err(const std::string& s) { g_last_error = s; }
 
+struct ProfRec {
+  std::string step;
+  int arith;
+  double flops;
+  hipEvent_t a, b;
+};
+thread_local bool g_prof_on = false;
+thread_local std::vector<ProfRec> g_prof;
+
 using mera::Arith;
 using mera::LabelDims;
 
@@ -55,6 +64,8 @@ struct Ctx {
   size_t off = 0;
   double flops = 0.0;
   hipError_t err = hipSuccess;
+  double* scratch = nullptr;  // split-k partial sums (see contract())
+  size_t scratch_elems = 0;
 
   size_t elem() const { return ar == Arith::F64 ? 8 : 4; }
   // reserve `count` elements of `bytes_per` bytes, 256-byte aligned
@@ -76,7 +87,24 @@ struct Ctx {
     }
     if (err != hipSuccess) return;
     const bool cf = (ar == Arith::F64) ? true : c_f64;
-    err = mera::contract(ar, dims, A, la, B, lb, C, lc, cf, alpha, beta, s, &flops);
+    ProfRec rec;
+    if (g_prof_on) {
+      rec.step = std::string(la) + "," + lb + "->" + lc;
+      rec.arith = (int)ar;
+      rec.flops = mera::contract_flops(dims, la, lb, lc);
+      if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) {
+        err = hipErrorOutOfMemory;
+        set_err("profile event creation failed");
+        return;
+      }
+      hipEventRecord(rec.a, s);
+    }
+    err = mera::contract(ar, dims, A, la, B, lb, C, lc, cf, alpha, beta, s, &flops, scratch,
+                         scratch_elems);
+    if (g_prof_on) {
+      hipEventRecord(rec.b, s);
+      g_prof.push_back(rec);
+    }
     if (err != hipSuccess)
       set_err(std::string("contract ") + la + "," + lb + "->" + lc + ": " + hipGetErrorString(err));
   }
@@ -125,11 +153,22 @@ void set_dims(Ctx& cx, int din, int dout) {
   cx.dims = LabelDims();
   cx.dims.set("pqrsPQRSabcdABCDxy", din);
   cx.dims.set("ijkIJK", dout);
+  // split-k scratch: 16 partial copies of the largest small-output contraction
+  // (din^4 * dout elements), in double
+  cx.scratch_elems = (size_t)16 * (size_t)ipow(din, 4) * (size_t)dout;
+  cx.scratch = cx.take_d(cx.scratch_elems);
 }
 
 // Shared small tensors of one layer.
+// N and M appear in several layouts so that every chi^9 contraction sums over
+// legs that are contiguous (in the same order) in both of its operands.
 struct Pieces {
-  void *Lp, *Rp, *N, *M;
+  void *Lp, *Rp;
+  void* N;   // [r s b d j]
+  void* N3;  // [r b s d j]
+  void* M;   // [p q c a j]
+  void* M1;  // [p q c j a]
+  void* M3;  // [p c q a j]
 };
 
 Pieces build_pieces(Ctx& cx, const LayerT& t, int64_t din, int64_t dout) {
@@ -137,18 +176,24 @@ Pieces build_pieces(Ctx& cx, const LayerT& t, int64_t din, int64_t dout) {
   pc.Lp = cx.take_t(din * din * dout * dout);
   pc.Rp = cx.take_t(din * din * dout * dout);
   pc.N = cx.take_t(ipow(din, 4) * dout);
+  pc.N3 = cx.take_t(ipow(din, 4) * dout);
   pc.M = cx.take_t(ipow(din, 4) * dout);
+  pc.M1 = cx.take_t(ipow(din, 4) * dout);
+  pc.M3 = cx.take_t(ipow(din, 4) * dout);
   cx.c(t.w, "xai", t.w, "xAI", pc.Lp, "aiAI", false, 1.0, 0.0);
   cx.c(t.w, "dyk", t.w, "DyK", pc.Rp, "dkDK", false, 1.0, 0.0);
   cx.c(t.w, "bcj", t.u, "rscd", pc.N, "rsbdj", false, 1.0, 0.0);
+  cx.c(t.w, "bcj", t.u, "rscd", pc.N3, "rbsdj", false, 1.0, 0.0);
   cx.c(t.u, "pqab", t.w, "bcj", pc.M, "pqcaj", false, 1.0, 0.0);
+  cx.c(t.u, "pqab", t.w, "bcj", pc.M1, "pqcja", false, 1.0, 0.0);
+  cx.c(t.u, "pqab", t.w, "bcj", pc.M3, "pcqaj", false, 1.0, 0.0);
   return pc;
 }
 
 // X[j a d A D J] = sum Lp[a i A I] rho[i j k I J K] Rp[d k D K]; keeps X1 = Lp.rho.
 void build_x(Ctx& cx, const Pieces& pc, const void* rho, void* X1, void* X) {
   cx.c(pc.Lp, "aiAI", rho, "ijkIJK", X1, "ajkAJK", false, 1.0, 0.0);
-  cx.c(X1, "ajkAJK", pc.Rp, "dkDK", X, "jadADJ", false, 1.0, 0.0);
+  cx.c(X1, "ajkAJK", pc.Rp, "dkDK", X, "djaADJ", false, 1.0, 0.0);
 }
 
 struct Bufs {
@@ -182,15 +227,15 @@ int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_
   const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
   bool first = true;
   if (placement != MERA_RIGHT) {
-    cx.c(pc.N, "rsbdj", X, "jadADJ", b.big, "rsbaADJ", false, 1.0, 0.0);
+    cx.c(pc.N, "rsbdj", X, "djaADJ", b.big, "rsbaADJ", false, 1.0, 0.0);
     cx.c(b.big, "rsbaADJ", pc.N, "RsBDJ", b.mid, "rabABR", false, 1.0, 0.0);
     cx.c(b.mid, "rabABR", t.u, "pqab", b.mid2, "pqrABR", false, 1.0, 0.0);
     cx.c(b.mid2, "pqrABR", t.u, "PQAB", rho_out, "pqrPQR", true, wgt, 0.0);
     first = false;
   }
   if (placement != MERA_LEFT) {
-    cx.c(pc.M, "pqcaj", X, "jadADJ", b.big, "pqcdADJ", false, 1.0, 0.0);
-    cx.c(b.big, "pqcdADJ", pc.M, "pQCAJ", b.mid, "qcdDCQ", false, 1.0, 0.0);
+    cx.c(pc.M1, "pqcja", X, "djaADJ", b.big, "pqcdDAJ", false, 1.0, 0.0);
+    cx.c(b.big, "pqcdDAJ", pc.M, "pQCAJ", b.mid, "qcdDCQ", false, 1.0, 0.0);
     cx.c(b.mid, "qcdDCQ", t.u, "rscd", b.mid2, "qrsCDQ", false, 1.0, 0.0);
     cx.c(b.mid2, "qrsCDQ", t.u, "RSCD", rho_out, "qrsQRS", true, wgt, first ? 0.0 : 1.0);
   }
@@ -213,18 +258,18 @@ int run_ascend(Ctx& cx, const mera_layer* L, const double* h_in, double* h_out, 
   bool first = true;
   if (placement != MERA_RIGHT) {
     cx.c(o, "pqrPQR", t.u, "PQAB", b.mid2, "pqrABR", false, wgt, 0.0);
-    cx.c(b.mid2, "pqrABR", t.u, "pqab", b.mid, "rabABR", false, 1.0, 0.0);
-    cx.c(b.mid, "rabABR", pc.N, "RsBDJ", b.big, "rsbaADJ", false, 1.0, 0.0);
-    cx.c(pc.N, "rsbdj", b.big, "rsbaADJ", Xb, "jadADJ", false, 1.0, 0.0);
+    cx.c(b.mid2, "pqrABR", t.u, "pqab", b.mid, "rabARB", false, 1.0, 0.0);
+    cx.c(b.mid, "rabARB", pc.N3, "RBsDJ", b.big, "rsbaADJ", false, 1.0, 0.0);
+    cx.c(pc.N, "rsbdj", b.big, "rsbaADJ", Xb, "djaADJ", false, 1.0, 0.0);
     first = false;
   }
   if (placement != MERA_LEFT) {
     cx.c(o, "qrsQRS", t.u, "RSCD", b.mid2, "qrsCDQ", false, wgt, 0.0);
     cx.c(b.mid2, "qrsCDQ", t.u, "rscd", b.mid, "qcdDCQ", false, 1.0, 0.0);
-    cx.c(b.mid, "qcdDCQ", pc.M, "pQCAJ", b.big, "pqcdADJ", false, 1.0, 0.0);
-    cx.c(pc.M, "pqcaj", b.big, "pqcdADJ", Xb, "jadADJ", false, 1.0, first ? 0.0 : 1.0);
+    cx.c(b.mid, "qcdDCQ", pc.M3, "pCQAJ", b.big, "pqcdADJ", false, 1.0, 0.0);
+    cx.c(pc.M, "pqcaj", b.big, "pqcdADJ", Xb, "djaADJ", false, 1.0, first ? 0.0 : 1.0);
   }
-  cx.c(Xb, "jadADJ", pc.Rp, "dkDK", Z1, "ajkAJK", false, 1.0, 0.0);
+  cx.c(Xb, "djaADJ", pc.Rp, "dkDK", Z1, "ajkAJK", false, 1.0, 0.0);
   cx.c(Z1, "ajkAJK", pc.Lp, "aiAI", h_out, "ijkIJK", true, 1.0, 0.0);
   return 0;
 }
@@ -265,45 +310,45 @@ int run_env(Ctx& cx, const mera_layer* L, const double* h_in, const double* rho_
     cx.c(h, "PQRpqr", t.u, "PQAB", b.mid2, "pqrABR", false, wgt, 0.0);  // G1
     if (want_u) {
       // forward Z = (N . X) . N' for the derivative of the closing ket uL
-      cx.c(pc.N, "rsbdj", X, "jadADJ", b.big, "rsbaADJ", false, 1.0, 0.0);
+      cx.c(pc.N, "rsbdj", X, "djaADJ", b.big, "rsbaADJ", false, 1.0, 0.0);
       cx.c(b.big, "rsbaADJ", pc.N, "RsBDJ", b.mid, "rabABR", false, 1.0, 0.0);
       acc_env(b.mid2, "pqrABR", b.mid, "rabABR", "pqab");
     }
-    cx.c(b.mid2, "pqrABR", t.u, "pqab", b.mid, "rabABR", false, 1.0, 0.0);   // G2
-    cx.c(b.mid, "rabABR", pc.N, "RsBDJ", b.big, "rsbaADJ", false, 1.0, 0.0);  // G3
-    cx.c(b.big, "rsbaADJ", X, "jadADJ", dN, "rsbdj", false, 1.0, 0.0);        // dN
+    cx.c(b.mid2, "pqrABR", t.u, "pqab", b.mid, "rabARB", false, 1.0, 0.0);   // G2
+    cx.c(b.mid, "rabARB", pc.N3, "RBsDJ", b.big, "rsbaADJ", false, 1.0, 0.0);  // G3
+    cx.c(b.big, "rsbaADJ", X, "djaADJ", dN, "rsbdj", false, 1.0, 0.0);        // dN
     if (want_u) {
       acc_env(dN, "rsbdj", t.w, "bcj", "rscd");  // uR inside N
     } else {
       acc_env(dN, "rsbdj", t.u, "rscd", "bcj");  // wC inside N
-      cx.c(pc.N, "rsbdj", b.big, "rsbaADJ", dX, "jadADJ", false, 1.0, 0.0);
+      cx.c(pc.N, "rsbdj", b.big, "rsbaADJ", dX, "djaADJ", false, 1.0, 0.0);
       first_dx = false;
     }
   }
   if (placement != MERA_LEFT) {
     cx.c(h, "QRSqrs", t.u, "RSCD", b.mid2, "qrsCDQ", false, wgt, 0.0);  // H1
     if (want_u) {
-      cx.c(pc.M, "pqcaj", X, "jadADJ", b.big, "pqcdADJ", false, 1.0, 0.0);
-      cx.c(b.big, "pqcdADJ", pc.M, "pQCAJ", b.mid, "qcdDCQ", false, 1.0, 0.0);
+      cx.c(pc.M1, "pqcja", X, "djaADJ", b.big, "pqcdDAJ", false, 1.0, 0.0);
+      cx.c(b.big, "pqcdDAJ", pc.M, "pQCAJ", b.mid, "qcdDCQ", false, 1.0, 0.0);
       acc_env(b.mid2, "qrsCDQ", b.mid, "qcdDCQ", "rscd");
     }
     cx.c(b.mid2, "qrsCDQ", t.u, "rscd", b.mid, "qcdDCQ", false, 1.0, 0.0);   // H2
-    cx.c(b.mid, "qcdDCQ", pc.M, "pQCAJ", b.big, "pqcdADJ", false, 1.0, 0.0);  // H3
-    cx.c(b.big, "pqcdADJ", X, "jadADJ", dM, "pqcaj", false, 1.0, 0.0);        // dM
+    cx.c(b.mid, "qcdDCQ", pc.M3, "pCQAJ", b.big, "pqcdADJ", false, 1.0, 0.0);  // H3
+    cx.c(b.big, "pqcdADJ", X, "djaADJ", dM, "pqcaj", false, 1.0, 0.0);        // dM
     if (want_u) {
       acc_env(dM, "pqcaj", t.w, "bcj", "pqab");  // uL inside M
     } else {
       acc_env(dM, "pqcaj", t.u, "pqab", "bcj");  // wC inside M
-      cx.c(pc.M, "pqcaj", b.big, "pqcdADJ", dX, "jadADJ", false, 1.0, first_dx ? 0.0 : 1.0);
+      cx.c(pc.M, "pqcaj", b.big, "pqcdADJ", dX, "djaADJ", false, 1.0, first_dx ? 0.0 : 1.0);
       first_dx = false;
     }
   }
   if (!want_u) {
     // isometries inside Lp and Rp (ket copies wL = w[x a i], wR = w[d y k])
-    cx.c(dX, "jadADJ", pc.Rp, "dkDK", V1, "ajkAJK", false, 1.0, 0.0);
+    cx.c(dX, "djaADJ", pc.Rp, "dkDK", V1, "ajkAJK", false, 1.0, 0.0);
     cx.c(V1, "ajkAJK", rho, "ijkIJK", dLp, "aiAI", false, 1.0, 0.0);
     acc_env(dLp, "aiAI", t.w, "xAI", "xai");
-    cx.c(X1, "ajkAJK", dX, "jadADJ", dRp, "dkDK", false, 1.0, 0.0);
+    cx.c(X1, "ajkAJK", dX, "djaADJ", dRp, "dkDK", false, 1.0, 0.0);
     acc_env(dRp, "dkDK", t.w, "DyK", "dyk");
   }
   return 0;
@@ -416,6 +461,42 @@ const char* mera_strerror(int status) {
 }
 
 const char* mera_last_error(void) { return g_last_error.c_str(); }
+
+int mera_profile_begin(void) {
+  for (auto& r : g_prof) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  g_prof_on = true;
+  return MERA_OK;
+}
+
+int mera_profile_end(mera_profile_entry* out, int32_t max_entries, int32_t* n_out) {
+  g_prof_on = false;
+  int rc = MERA_OK;
+  int32_t n = 0;
+  for (auto& r : g_prof) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      set_err("profile event query failed");
+      rc = MERA_EDEVICE;
+    }
+    if (out && n < max_entries) {
+      std::memset(out[n].step, 0, sizeof(out[n].step));
+      std::strncpy(out[n].step, r.step.c_str(), sizeof(out[n].step) - 1);
+      out[n].arith = r.arith;
+      out[n].flops = r.flops;
+      out[n].ms = ms;
+      ++n;
+    }
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  if (n_out) *n_out = n;
+  return rc;
+}
 
 int mera_descend(const mera_layer* layer, const double* rho_in_d, double* rho_out_d, int placement,
                  int precision, void* ws_d, size_t ws_bytes, void* hip_stream) {

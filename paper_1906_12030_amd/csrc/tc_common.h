@@ -23,12 +23,15 @@ struct TcArgs {
   const void* a;
   const void* b;
   void* c;
+  double* part;  // split-k partial sums, dense [splits][M][N] (used when splits > 1)
   int32_t M, N, K;
   Group gm;  // x = A, y = C
   Group gn;  // x = B, y = C
   Group gk;  // x = A, y = B
   double alpha, beta;
   int32_t tiles_m, tiles_n, per_xcd, group_m;
+  int32_t splits, kchunk;  // k range of split s: [s*kchunk, min(K, (s+1)*kchunk))
+  int32_t cvec;            // 64-wide output column spans are contiguous (vector stores)
 };
 
 // Offset of linear group index idx in operand x (Second = false) or y.
@@ -53,13 +56,15 @@ __device__ __forceinline__ int64_t goff(const Group& g, uint32_t idx) {
 // XCD owns a contiguous range of logical tiles, then walk that range in groups
 // of group_m tile rows (column-major inside a group) so that concurrently
 // running workgroups of one XCD share A and B panels in its L2.
-__device__ __forceinline__ bool tile_of_block(const TcArgs& p, int& tm, int& tn) {
+__device__ __forceinline__ bool tile_of_block(const TcArgs& p, int& tm, int& tn, int& split) {
   const int bid = blockIdx.x;
   const int xcd = bid & 7;
   const int idx = bid >> 3;
-  const int logical = xcd * p.per_xcd + idx;
+  int logical = xcd * p.per_xcd + idx;
   const int total = p.tiles_m * p.tiles_n;
-  if (logical >= total) return false;
+  if (logical >= total * p.splits) return false;
+  split = logical / total;
+  logical -= split * total;
   const int gsz_full = p.group_m * p.tiles_n;
   const int group = logical / gsz_full;
   const int first_m = group * p.group_m;
@@ -70,7 +75,264 @@ __device__ __forceinline__ bool tile_of_block(const TcArgs& p, int& tm, int& tn)
   return true;
 }
 
-hipError_t launch_contract_b3(const TcArgs& a, bool akc, bool va, bool bnc, bool vb, bool c_f64,
-                              hipStream_t s);
+hipError_t launch_contract_b3(const TcArgs& a, bool akc, bool va, bool bnc, bool vb, bool kal,
+                              bool c_f64, hipStream_t s);
+
+}  // namespace mera
+
+namespace mera {
+
+constexpr int kThreads = 256;
+
+template <typename T, int V>
+__device__ __forceinline__ void load_vec(const T* p, T* out) {
+  if constexpr (V == 1) {
+    out[0] = *p;
+  } else {
+    typedef T vt __attribute__((ext_vector_type(V)));
+    const vt v = *reinterpret_cast<const vt*>(p);
+#pragma unroll
+    for (int i = 0; i < V; ++i) out[i] = v[i];
+  }
+}
+
+// Registers-side loader of one operand tile: ROWS rows (m for A, n for B) by
+// BK k-columns.  KC: the operand is contiguous along k (each thread loads V
+// consecutive k of one row); otherwise contiguous along the rows (V
+// consecutive rows at one k).  KSecond selects the operand's k strides in the
+// k group (A: first, B: second).  KAL: the innermost k leg's extent is a
+// multiple of BK, so a whole k-tile lies in one run of that leg and its
+// offsets are a uniform base plus a per-thread constant; otherwise every
+// k offset is decomposed leg by leg (and masked against K).
+template <typename T, int ROWS, int BK, bool KC, int V, bool KAL, bool KSecond>
+struct TileLoad {
+  static constexpr int TPL = KC ? BK / V : ROWS / V;  // threads per line
+  static constexpr int LPP = kThreads / TPL;          // lines per pass
+  static constexpr int NP = KC ? ROWS / LPP : BK / LPP;
+  static_assert(NP >= 1 && LPP * TPL == kThreads, "tile geometry");
+  static constexpr int NR = KC ? NP : 1;  // row offsets held per thread
+  static constexpr int NK = KC ? 1 : NP;  // k lines per thread
+
+  int line, vec;
+  int64_t roff[NR];
+  bool rok[NR];
+  int64_t kd[NK];  // KAL: offset of this thread's k (or k lines) from the k-tile base
+  T r[NP][V];
+
+  __device__ __forceinline__ void init(const Group& grow, const Group& gk, uint32_t row0,
+                                       uint32_t nrows) {
+    const int tid = threadIdx.x;
+    line = tid / TPL;
+    vec = (tid % TPL) * V;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const uint32_t rr = KC ? row0 + line + i * LPP : row0 + vec;
+      rok[i] = rr < nrows;
+      // rows past the end read a valid element instead (their products only
+      // reach output rows that are never stored)
+      roff[i] = rok[i] ? goff<false>(grow, rr) : 0;
+    }
+    const int64_t si = KSecond ? gk.sy[gk.nd - 1] : gk.sx[gk.nd - 1];
+#pragma unroll
+    for (int i = 0; i < NK; ++i) kd[i] = KC ? (int64_t)vec * si : (int64_t)(line + i * LPP) * si;
+  }
+
+  // k-aligned tile whose k offset (uniform) is kb: no masking at all
+  __device__ __forceinline__ void load_at(const T* __restrict__ base, int64_t kb) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) load_vec<T, V>(base + roff[KC ? i : 0] + kb + kd[KC ? 0 : i], r[i]);
+  }
+
+  __device__ __forceinline__ void load(const T* __restrict__ base, const Group& gk, uint32_t k0,
+                                       uint32_t K) {
+    if constexpr (KAL) {
+      const int64_t kb = goff<KSecond>(gk, k0);
+      load_at(base, kb);
+    } else {
+      if constexpr (KC) {
+        const uint32_t k = k0 + vec;
+        const bool kok = k < K;
+        const int64_t ko = kok ? goff<KSecond>(gk, k) : 0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          if (kok && rok[i]) {
+            load_vec<T, V>(base + roff[i] + ko, r[i]);
+          } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) r[i][v] = T(0);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          const uint32_t k = k0 + line + i * LPP;
+          if (k < K && rok[0]) {
+            load_vec<T, V>(base + roff[0] + goff<KSecond>(gk, k), r[i]);
+          } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) r[i][v] = T(0);
+          }
+        }
+      }
+    }
+  }
+};
+
+// Uniform walk over k-tiles of a k group whose innermost leg's extent is a
+// multiple of the tile: keeps the leg digits of the tile start and its offsets
+// in both operands, advancing by carries instead of divisions.
+template <int BK>
+struct KWalk {
+  int32_t dig[kMaxDims];
+  int64_t oa, ob;
+  __device__ __forceinline__ void init(const Group& g, uint32_t k0) {
+    oa = 0;
+    ob = 0;
+#pragma unroll
+    for (int d = kMaxDims - 1; d >= 0; --d) {
+      dig[d] = 0;
+      if (d < g.nd) {
+        const uint32_t sz = (uint32_t)g.size[d];
+        const uint32_t q = k0 / sz;
+        dig[d] = (int32_t)(k0 - q * sz);
+        oa += (int64_t)dig[d] * g.sx[d];
+        ob += (int64_t)dig[d] * g.sy[d];
+        k0 = q;
+      }
+    }
+  }
+  __device__ __forceinline__ void next(const Group& g) {
+    const int in = g.nd - 1;
+    // innermost leg (index known only at run time; unrolled over the legal range)
+#pragma unroll
+    for (int d = kMaxDims - 1; d >= 0; --d) {
+      if (d == in) {
+        dig[d] += BK;
+        oa += (int64_t)BK * g.sx[d];
+        ob += (int64_t)BK * g.sy[d];
+      }
+    }
+    // carries toward the outer legs
+#pragma unroll
+    for (int d = kMaxDims - 1; d >= 1; --d) {
+      if (d <= in && dig[d] >= g.size[d]) {
+        dig[d] -= g.size[d];
+        oa += g.sx[d - 1] - (int64_t)g.size[d] * g.sx[d];
+        ob += g.sy[d - 1] - (int64_t)g.size[d] * g.sy[d];
+        dig[d - 1] += 1;
+      }
+    }
+  }
+};
+
+// Output offsets of the tile's rows and columns in LDS (-1 = outside the
+// matrix).  Split-k launches write dense partial sums instead.
+template <int TM, int TN>
+__device__ __forceinline__ void stage_c_offsets(const TcArgs& p, uint32_t m0, uint32_t n0, int split,
+                                                int64_t* rows, int64_t* cols) {
+  const int t = threadIdx.x;
+  for (int i = t; i < TM + TN; i += kThreads) {
+    if (i < TM) {
+      const uint32_t m = m0 + i;
+      int64_t o = -1;
+      if (m < (uint32_t)p.M)
+        o = p.splits > 1 ? ((int64_t)split * p.M + m) * p.N : goff<true>(p.gm, m);
+      rows[i] = o;
+    } else {
+      const uint32_t n = n0 + (i - TM);
+      int64_t o = -1;
+      if (n < (uint32_t)p.N) o = p.splits > 1 ? (int64_t)n : goff<true>(p.gn, n);
+      cols[i - TM] = o;
+    }
+  }
+}
+
+// Epilogue shared by the MFMA kernels.  Each wave owns a 64x64 block of the
+// 128x128 tile held as 4x4 MFMA 16x16 accumulators; row-group by row-group
+// (16 rows) the wave parks its accumulators in LDS and re-reads them so that
+// each lane stores 16 contiguous bytes and 16 lanes cover one 64-wide row
+// span.  ROWF(lane, r) is the row of accumulator register r within a 16x16
+// block.  LDS needs 2 KB of offset tables plus 4 x 16 x (64+pad) accumulators.
+template <typename AT, typename TC, typename ACC, typename ROWF>
+__device__ __forceinline__ void write_tile(const TcArgs& p, ACC (&acc)[4][4], uint32_t m0,
+                                           uint32_t n0, int split, char* lds, ROWF rowf) {
+  constexpr int VA = 16 / sizeof(AT);  // accumulator elements per 16-byte read
+  constexpr int PADE = VA;
+  constexpr int LD = 64 + PADE;
+  int64_t* rows = reinterpret_cast<int64_t*>(lds);
+  int64_t* cols = rows + 128;
+  AT* stage = reinterpret_cast<AT*>(lds + 2048);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 64;
+  const int wn = (wave & 1) * 64;
+  AT* st = stage + wave * 16 * LD;
+  stage_c_offsets<128, 128>(p, m0, n0, split, rows, cols);
+  TC* __restrict__ C = p.splits > 1 ? reinterpret_cast<TC*>(p.part) : static_cast<TC*>(p.c);
+  const double alpha = p.splits > 1 ? 1.0 : p.alpha;
+  const double beta = p.splits > 1 ? 0.0 : p.beta;
+  const bool vec = p.cvec != 0;
+  for (int i = 0; i < 4; ++i) {
+    __syncthreads();  // offsets staged / previous row group consumed
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) st[rowf(lane, r) * LD + j * 16 + (lane & 15)] = (AT)acc[i][j][r];
+    __syncthreads();
+    constexpr int PER_ROW = 64 / VA;          // 16-byte vectors per 64-wide row
+    constexpr int ITER = 16 * PER_ROW / 64;   // vectors per lane
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int idx = it * 64 + lane;
+      const int row = idx / PER_ROW;
+      const int col = (idx % PER_ROW) * VA;
+      const int64_t ro = rows[wm + i * 16 + row];
+      if (ro < 0) continue;
+      AT v[VA];
+      typedef AT vt __attribute__((ext_vector_type(VA)));
+      const vt x = *reinterpret_cast<const vt*>(&st[row * LD + col]);
+#pragma unroll
+      for (int e = 0; e < VA; ++e) v[e] = x[e];
+      const int64_t co = cols[wn + col];
+      if (vec && co >= 0) {
+        TC* dst = C + ro + co;
+        TC out[VA];
+#pragma unroll
+        for (int e = 0; e < VA; ++e) {
+          double y = alpha * (double)v[e];
+          if (beta != 0.0) y += beta * (double)dst[e];
+          out[e] = (TC)y;
+        }
+        if constexpr (sizeof(TC) * VA == 16) {
+          typedef TC ot __attribute__((ext_vector_type(VA)));
+          ot o;
+#pragma unroll
+          for (int e = 0; e < VA; ++e) o[e] = out[e];
+          *reinterpret_cast<ot*>(dst) = o;
+        } else {  // 4 doubles from float accumulators: two 16-byte stores
+          typedef TC ot __attribute__((ext_vector_type(2)));
+#pragma unroll
+          for (int h = 0; h < VA / 2; ++h) {
+            ot o;
+            o[0] = out[2 * h];
+            o[1] = out[2 * h + 1];
+            *reinterpret_cast<ot*>(dst + 2 * h) = o;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < VA; ++e) {
+          const int64_t ce = cols[wn + col + e];
+          if (ce < 0) continue;
+          TC* dst = C + ro + ce;
+          double y = alpha * (double)v[e];
+          if (beta != 0.0) y += beta * (double)(*dst);
+          *dst = (TC)y;
+        }
+      }
+    }
+  }
+}
 
 }  // namespace mera

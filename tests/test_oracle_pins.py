@@ -354,3 +354,13 @@ def test_scaling_dimension_of_identity_is_zero():
     u, w = I.random_layer(rng, 2, 2)
     dims, lam = O.scaling_dimensions(u, w, k=4)
     assert abs(dims[0]) < 1e-12 and abs(lam[0] - 1) < 1e-12
+
+
+def test_descend_slice_is_a_slice():
+    rng = np.random.default_rng(12)
+    u, w = I.random_layer(rng, 3, 3)
+    rho = I.random_density(rng, 3)
+    for p in ("L", "R"):
+        full = O.descend_placement(u, w, rho, p)
+        for k in range(3):
+            assert np.abs(O.descend_placement_slice(u, w, rho, p, k) - full[k]).max() < 1e-14
