@@ -106,10 +106,14 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e_mixed = None
+    e_first = None
     for k in range(args.steps):
         e, c = sweep.sweep(m, h1, shift, args.iters, prec)
         e_mixed = e
+        if k == 0:
+            e_first = e
     torch.cuda.synchronize()
+    e_first = float(e_first.item()) + shift
     t_mixed = (time.perf_counter() - t0) / args.steps
     st, recs = _lib.mera_profile_end()
     e_mixed = float(e_mixed.item()) + shift
@@ -146,10 +150,12 @@ def main():
         mm = sweep.GpuMera([(u.clone(), w.clone()) for u, w in m.layers], (m.si[0].clone(), m.si[1].clone()),
                            m.rho_star.clone())
         sweep.initial_fixed_point(mm, args.iters, precision)
-        return sweep.energy(mm, h1, shift, precision)
+        return sweep.energy(mm, h1, shift)
 
     e_eval_mixed = eval_energy(prec)
     e_eval_fp64 = eval_energy("fp64")
+    # both evaluations: rho* by args.iters steps from the same warm start (the
+    # mixed one in FP64 iterative-refinement form), FP64 descent and trace
     print(f"# energy at final tensors: mixed {e_eval_mixed:.15f}  fp64 {e_eval_fp64:.15f}", file=sys.stderr, flush=True)
 
     cpu = None
@@ -184,7 +190,9 @@ def main():
         "sweep_flops": flops,
         "contraction_tflops_all_launches": round(all_f / (all_ms / 1e3) / 1e12, 3),
         "energy_after_mixed_sweeps": e_mixed,
-        "energy_after_one_fp64_sweep_from_same_start": e_fp64,
+        "energy_after_one_sweep_mixed": e_first,
+        "energy_after_one_sweep_fp64": e_fp64,
+        "dE_one_sweep_same_start": abs(e_first - e_fp64) if e_fp64 is not None else None,
         "energy_eval_final_tensors_mixed": e_eval_mixed,
         "energy_eval_final_tensors_fp64": e_eval_fp64,
         "dE_eval": abs(e_eval_mixed - e_eval_fp64),

@@ -124,9 +124,16 @@ int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* o
                       int32_t* iters_out, void* ws_d, size_t ws_bytes, void* hip_stream);
 
 /* Fixed point of the scale-invariant descending superoperator (Sec. II.B):
- * `iters` steps of rho <- D_AVG(rho), rho <- (rho + rho^T)/2, rho <- rho/tr(rho)
- * with D in `precision` and the symmetrisation and renormalisation in FP64.
- * rho_d (d^6) holds the warm start on entry and the result on exit.
+ * `iters` power-iteration steps rho <- D_AVG(rho), rho <- (rho + rho^T)/2,
+ * rho <- rho/tr(rho), with the symmetrisation and renormalisation in FP64.
+ * MERA_FP64 runs exactly that.  MERA_FP32 / MERA_BF16X3 run it in
+ * iterative-refinement form, in cycles of up to 30 steps: one FP64 residual
+ * r = D(rho) - rho, then delta <- D_lp(delta) + r with the reduced-precision D,
+ * then rho <- normalise(sym(rho + delta)).  In exact arithmetic a cycle of L
+ * steps equals L power-iteration steps; the reduced-precision error is
+ * proportional to ||delta|| rather than ||rho||, so repeated calls converge to
+ * the FP64 fixed point.  rho_d (d^6) holds the warm start on entry and the
+ * result on exit.
  * resid_d (device, nullable, 1 double) receives ||rho_k - rho_{k-1}||_F /
  * ||rho_k||_F of the last step.  layer->din must equal layer->dout. */
 int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int precision,

@@ -27,6 +27,7 @@
 // reverse-mode derivatives of e = tr(h D(rho)) with respect to the ket copies.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -675,31 +676,78 @@ int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int
   }
   const int64_t d = si->din;
   const int64_t n = d * d * d;
+  const int64_t nn = n * n;
   Ctx cx;
-  cx.ar = arith_of(precision);
+  const Arith lp = arith_of(precision);
+  cx.ar = lp;
+  // FP64: plain power iteration.  Reduced precision: cycles of at most
+  // kRefineCycle descends in the iterative-refinement form
+  //   r = D64(rho) - rho,  delta <- D_lp(delta) + r  (L-1 times, delta_1 = r),
+  //   rho <- normalise(sym(rho + delta)),
+  // which in exact arithmetic equals L power-iteration steps
+  // (rho + sum_{k<L} D^k r = D^L rho) while the low-precision products only
+  // act on the correction, so their error scales with ||delta||, not ||rho||.
+  constexpr int kRefineCycle = 30;
   auto body = [&](Ctx& c) {
-    double* tmp = c.take_d(n * n);
-    double* prev = resid_d ? c.take_d(n * n) : nullptr;
+    double* tmp = c.take_d(nn);
+    double* prev = resid_d ? c.take_d(nn) : nullptr;
+    double* r = lp != Arith::F64 ? c.take_d(nn) : nullptr;
+    double* dl = lp != Arith::F64 ? c.take_d(nn) : nullptr;
     double* partial = c.take_d(mera::kReduceBlocks);
     double* scal = c.take_d(4);
     const size_t mark = c.off;
-    for (int it = 0; it < iters; ++it) {
-      c.off = mark;  // the descend workspace is reused by every iteration
-      run_descend(c, si, rho_d, tmp, MERA_AVG);
-      if (c.dry) {
-        if (it > 0) break;  // size and flops of one iteration suffice in a dry pass
-        continue;
+    // one descend in arithmetic a; the descend workspace is reused every time
+    auto D = [&](Arith a, const double* in, double* out) {
+      c.off = mark;
+      const Arith save = c.ar;
+      c.ar = a;
+      run_descend(c, si, in, out, MERA_AVG);
+      c.ar = save;
+    };
+    if (c.dry) {  // size the workspace for both arithmetics; count one iteration
+      if (iters > 0) {
+        D(Arith::F64, rho_d, tmp);
+        const size_t hi = c.off;
+        if (lp != Arith::F64) D(lp, rho_d, tmp);
+        c.off = std::max(hi, c.off);
       }
-      c.check(mera::launch_reduce(2, tmp, nullptr, n, partial, scal, c.s), "trace");
-      if (resid_d && it == iters - 1) c.check(hipMemcpyAsync(prev, rho_d, n * n * 8, hipMemcpyDeviceToDevice, c.s), "copy");
-      c.check(mera::launch_sym_normalize(tmp, rho_d, n, scal, c.s), "symmetrise");
+      return;
     }
-    if (!c.dry && resid_d) {
+    auto finish = [&](double* next, bool last) {
+      // rho <- (next + next^T) / tr(next), in FP64
+      c.check(mera::launch_reduce(2, next, nullptr, n, partial, scal, c.s), "trace");
+      if (resid_d && last) c.check(hipMemcpyAsync(prev, rho_d, nn * 8, hipMemcpyDeviceToDevice, c.s), "copy");
+      c.check(mera::launch_sym_normalize(next, rho_d, n, scal, c.s), "symmetrise");
+    };
+    if (lp == Arith::F64) {
+      for (int it = 0; it < iters; ++it) {
+        D(Arith::F64, rho_d, tmp);
+        finish(tmp, it == iters - 1);
+      }
+    } else {
+      int done = 0;
+      while (done < iters) {
+        const int L = std::min(kRefineCycle, iters - done);
+        D(Arith::F64, rho_d, tmp);                                          // D64(rho)
+        c.check(mera::launch_scale(tmp, r, 1.0, nn, c.s), "copy");          // r = D64(rho)
+        c.check(mera::launch_axpby(rho_d, r, -1.0, 1.0, nn, c.s), "resid");  // r -= rho
+        c.check(mera::launch_scale(r, dl, 1.0, nn, c.s), "copy");           // delta = r
+        for (int j = 1; j < L; ++j) {
+          D(lp, dl, tmp);                                                   // D_lp(delta)
+          c.check(mera::launch_axpby(r, tmp, 1.0, 1.0, nn, c.s), "acc");    // + r
+          std::swap(dl, tmp);
+        }
+        c.check(mera::launch_axpby(rho_d, dl, 1.0, 1.0, nn, c.s), "update");  // rho + delta
+        done += L;
+        finish(dl, done >= iters);
+      }
+    }
+    if (resid_d) {
       if (iters == 0) {
         c.check(mera::launch_fill(resid_d, 0.0, 1, c.s), "fill");
       } else {
-        c.check(mera::launch_reduce(1, rho_d, prev, n * n, partial, scal + 1, c.s), "diff");
-        c.check(mera::launch_reduce(4, rho_d, nullptr, n * n, partial, scal + 2, c.s), "norm");
+        c.check(mera::launch_reduce(1, rho_d, prev, nn, partial, scal + 1, c.s), "diff");
+        c.check(mera::launch_reduce(4, rho_d, nullptr, nn, partial, scal + 2, c.s), "norm");
         c.check(mera::launch_sqrt_ratio(scal + 1, scal + 2, resid_d, c.s), "ratio");
       }
     }
@@ -790,11 +838,25 @@ size_t mera_workspace_bytes(int op, int32_t din, int32_t dout, int precision, in
     case MERA_OP_FIXED_POINT: {
       if (din != dout) return 0;
       const int64_t n = (int64_t)din * din * din;
-      cx.take_d(n * n);
-      cx.take_d(n * n);
+      const bool refine = precision != MERA_FP64;
+      cx.take_d(n * n);                  // tmp
+      cx.take_d(n * n);                  // prev (residual output)
+      if (refine) {
+        cx.take_d(n * n);                // r
+        cx.take_d(n * n);                // delta
+      }
       cx.take_d(mera::kReduceBlocks);
       cx.take_d(4);
+      const size_t mark = cx.off;
+      cx.ar = Arith::F64;
       run_descend(cx, &L, dummy, out, MERA_AVG);
+      const size_t hi = cx.off;
+      if (refine) {
+        cx.off = mark;
+        cx.ar = arith_of(precision);
+        run_descend(cx, &L, dummy, out, MERA_AVG);
+      }
+      cx.off = std::max(hi, cx.off);
       break;
     }
     default: return 0;

@@ -13,8 +13,9 @@ layers layer by layer"; the rest is this implementation's reading):
   4. transitional layers top-down: u then w from (h_t, rho_{t+1}), then
      rho_t = D_t(rho_{t+1}) with the updated tensors;
   5. energy per site tr(h_1 rho_1) + shift.
-Contractions run in ``precision``; polar updates, the fixed-point
-renormalisation and the energy are FP64 in every mode.
+Contractions run in ``precision``; polar updates, the fixed-point residual and
+renormalisation (iterative refinement, see mera_fixed_point_rho), the descent
+of rho* through the transitional layers and the energy are FP64 in every mode.
 """
 from __future__ import annotations
 
@@ -70,16 +71,18 @@ def ascend_chain(m: GpuMera, h1: torch.Tensor, precision="fp64"):
     return hs
 
 
-def descend_chain(m: GpuMera, precision="fp64"):
+def descend_chain(m: GpuMera):
+    """rho_t for every level, descended from rho* in FP64 (the transitional
+    descends are a few per cent of a sweep, so every mode keeps them exact)."""
     rhos = [m.rho_star]
     for t in reversed(range(len(m.layers))):
-        rhos.append(ops.descend(m.layer(t), rhos[-1], "avg", precision))
+        rhos.append(ops.descend(m.layer(t), rhos[-1], "avg", "fp64"))
     return rhos[::-1]
 
 
-def energy(m: GpuMera, h1: torch.Tensor, shift: float, precision="fp64") -> float:
-    """Energy per site of the current state (rho* as stored)."""
-    rho1 = descend_chain(m, precision)[0]
+def energy(m: GpuMera, h1: torch.Tensor, shift: float) -> float:
+    """Energy per site of the current state (rho* as stored), FP64 descent and trace."""
+    rho1 = descend_chain(m)[0]
     return float(ops.energy(h1, rho1).item()) + shift
 
 
@@ -131,7 +134,7 @@ def sweep(m: GpuMera, h1: torch.Tensor, shift: float, iters=30, precision="fp64"
         lay = m.layer(t)
         m.layers[t][1] = ops.update_w(ops.env_w(lay, hs[t], rho, "avg", precision))
         lay = m.layer(t)
-        rho = ops.descend(lay, rho, "avg", precision)
+        rho = ops.descend(lay, rho, "avg", "fp64")
     mark("transitional")
     e = ops.energy(h1, rho)
     mark("end")
