@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed sweeps only (for external profilers)")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="one split-bf16 descend at --chi plus a 1 GiB device copy (for HBM counters)")
     return ap.parse_args()
 
 
@@ -74,6 +76,30 @@ def cpu_baseline(chi: int, seed: int) -> dict:
                       f"(1/{chi} of a left-window descend, {flops:.3e} flop in the GPU schedule's count)"}
 
 
+def traffic_probe(args):
+    """Kernels for the FETCH_SIZE / WRITE_SIZE counter runs: one descend call in the
+    benchmark precision (its chi^9 launches are the dominant kernel) and a plain
+    copy of a known size (2^27 doubles) that calibrates the counters."""
+    import torch
+
+    from paper_1906_12030_amd import inputs, ops
+
+    chi = args.chi
+    layers, si = inputs.init_mera(chi, 0, args.seed)
+    lay = ops.Layer(torch.from_numpy(si[0]).cuda(), torch.from_numpy(si[1]).cuda())
+    n = chi ** 3
+    g = torch.randn(n, 64, dtype=torch.float64, device="cuda")
+    rho = (g @ g.t()).div_(n).reshape((chi,) * 6).contiguous()
+    out = ops.descend(lay, rho, "avg", args.precision)
+    torch.cuda.synchronize()
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"traffic_probe": True, "chi": chi, "precision": args.precision,
+                      "copy_bytes": 8 << 27, "check": float(out.reshape(-1)[0].item())}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -86,6 +112,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.traffic_probe:
+        traffic_probe(args)
+        return
     chi, T = args.chi, args.layers
     m = sweep.GpuMera.seeded(chi, T, args.seed)
     h1, shift = ops.tfim_hamiltonian(1.0)
