@@ -19,6 +19,23 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# HBM traffic per chi^9 split-bf16 launch at chi=24, from the FETCH_SIZE / WRITE_SIZE
+# counter runs summarised in profiles/b3_contraction_traffic_chi24.md (copy-calibrated).
+# Valid only for the kernel sources it was measured on (hash of csrc/*).
+TRAFFIC_RECORD = {"source_hash": "8f7df714ebf7303f", "bytes_per_launch": 57.35e9}
+
+
+def kernel_source_hash() -> str:
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1906_12030_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 PEAK = {  # MI355X published dense peaks, TFLOP/s
     "fp64": 78.6,
     "fp32": 157.3,
@@ -84,9 +101,11 @@ def traffic_probe(args):
 
     from paper_1906_12030_amd import inputs, ops
 
+    import numpy as np
+
     chi = args.chi
-    layers, si = inputs.init_mera(chi, 0, args.seed)
-    lay = ops.Layer(torch.from_numpy(si[0]).cuda(), torch.from_numpy(si[1]).cuda())
+    u, w = inputs.random_layer(np.random.default_rng(args.seed), chi, chi)
+    lay = ops.Layer(torch.from_numpy(u).cuda(), torch.from_numpy(w).cuda())
     n = chi ** 3
     g = torch.randn(n, 64, dtype=torch.float64, device="cuda")
     rho = (g @ g.t()).div_(n).reshape((chi,) * 6).contiguous()
@@ -194,6 +213,9 @@ def main():
 
     value = flops["total"] / t_mixed / 1e12
     roof_peak = PEAK["bf16"] / 3.0 if prec == "bf16x3" else PEAK[prec]
+    traffic = None
+    if prec == "bf16x3" and chi == 24 and kernel_source_hash() == TRAFFIC_RECORD["source_hash"]:
+        traffic = TRAFFIC_RECORD["bytes_per_launch"]
     achieved = big_f / (big_ms / 1e3) / 1e12
     out = {
         "metric": "MERA sweep s & env-contraction TFLOP/s at chi=24, mixed vs FP64, |dE|<=1e-9",
@@ -226,7 +248,8 @@ def main():
         "energy_eval_final_tensors_fp64": e_eval_fp64,
         "dE_eval": abs(e_eval_mixed - e_eval_fp64),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(roof_peak, 1),
-                     "unit": "TFLOP/s", "frac": round(achieved / roof_peak, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / roof_peak, 4), "traffic": traffic,
+                     "traffic_unit": "bytes per launch (HBM, copy-calibrated FETCH_SIZE + WRITE_SIZE)",
                      "kernel": f"chi^9 contraction launches ({prec}), {len(big)} launches, "
                                f"{big_f / len(big):.3e} flop each, avg {big_ms / len(big):.3f} ms",
                      "note": "split-bf16 peak = bf16 dense MFMA peak / 3 (three bf16 products per useful multiply-add)"
