@@ -173,6 +173,14 @@ typedef struct {
 int mera_profile_begin(void);
 int mera_profile_end(mera_profile_entry* out, int32_t max_entries, int32_t* n_out);
 
+/* Smallest workspace with which `op` still runs: for MERA_OP_DESCEND and
+ * MERA_OP_FIXED_POINT the chi^7 intermediates can be processed in slices of
+ * an open leg (fine site 3 for the left window, site 2 for the right one);
+ * given less than mera_workspace_bytes() but at least this much, those calls
+ * pick the smallest slice count that fits.  Equal to mera_workspace_bytes()
+ * for the other ops.  Pure host function. */
+size_t mera_workspace_bytes_min(int op, int32_t din, int32_t dout, int precision, int placement);
+
 /* Static text for a status code. */
 const char* mera_strerror(int status);
 

@@ -22,6 +22,7 @@ EXPORTED = (
     "mera_ascend", "mera_descend", "mera_env_u", "mera_env_w", "mera_polar_update",
     "mera_fixed_point_rho", "mera_energy", "mera_tfim_hamiltonian", "mera_workspace_bytes",
     "mera_strerror", "mera_last_error", "mera_flops", "mera_profile_begin", "mera_profile_end",
+    "mera_workspace_bytes_min",
 )
 
 
@@ -64,6 +65,8 @@ def load() -> ctypes.CDLL:
     lib.mera_tfim_hamiltonian.argtypes = [dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.mera_workspace_bytes.argtypes = [ctypes.c_int, i32, i32, ctypes.c_int, ctypes.c_int]
     lib.mera_workspace_bytes.restype = sz
+    lib.mera_workspace_bytes_min.argtypes = [ctypes.c_int, i32, i32, ctypes.c_int, ctypes.c_int]
+    lib.mera_workspace_bytes_min.restype = sz
     lib.mera_flops.argtypes = [ctypes.c_int, i32, i32, ctypes.c_int]
     lib.mera_flops.restype = dbl
     lib.mera_strerror.argtypes = [ctypes.c_int]
@@ -128,6 +131,10 @@ def mera_tfim_hamiltonian(field):
 
 def mera_workspace_bytes(op, din, dout, precision, placement):
     return int(load().mera_workspace_bytes(op, din, dout, precision, placement))
+
+
+def mera_workspace_bytes_min(op, din, dout, precision, placement):
+    return int(load().mera_workspace_bytes_min(op, din, dout, precision, placement))
 
 
 def mera_flops(op, din, dout, placement):

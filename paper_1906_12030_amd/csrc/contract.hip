@@ -206,12 +206,12 @@ bool contains(const std::string& s, char c) { return s.find(c) != std::string::n
 // Build a group from legs (outer..inner) with strides in operands X and Y,
 // merging neighbours that are contiguous in both.
 bool build_group(const std::string& legs, const std::string& lx, const std::string& ly,
-                 const LabelDims& dims, Group& g, int64_t& total) {
+                 const LabelDims& dims, const LabelDims& ydims, Group& g, int64_t& total) {
   std::vector<int64_t> sz, sx, sy;
   for (char c : legs) {
     sz.push_back(dims.d[(unsigned char)c]);
     sx.push_back(stride_in(lx, c, dims));
-    sy.push_back(stride_in(ly, c, dims));
+    sy.push_back(stride_in(ly, c, ydims));
   }
   // merge from inner to outer
   std::vector<int64_t> msz, msx, msy;
@@ -311,7 +311,8 @@ double contract_flops(const LabelDims& dims, const char* la_, const char* lb_, c
 hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* la_, const void* B,
                     const char* lb_, void* C, const char* lc_, bool c_f64, double alpha,
                     double beta, hipStream_t stream, double* flops, double* scratch,
-                    size_t scratch_elems) {
+                    size_t scratch_elems, const LabelDims* cdims) {
+  const LabelDims& cd = cdims ? *cdims : dims;
   std::string la(la_), lb(lb_), lc(lc_);
   // C's innermost leg must come from "B" so that stores run along n.
   if (!lc.empty() && contains(la, lc.back()) && !contains(lb, lc.back())) {
@@ -351,9 +352,9 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
   TcArgs args;
   std::memset(&args, 0, sizeof(args));
   int64_t M, N, K;
-  if (!build_group(mlab, la, lc, dims, args.gm, M)) return hipErrorInvalidValue;
-  if (!build_group(nlab, lb, lc, dims, args.gn, N)) return hipErrorInvalidValue;
-  if (!build_group(klab, la, lb, dims, args.gk, K)) return hipErrorInvalidValue;
+  if (!build_group(mlab, la, lc, dims, cd, args.gm, M)) return hipErrorInvalidValue;
+  if (!build_group(nlab, lb, lc, dims, cd, args.gn, N)) return hipErrorInvalidValue;
+  if (!build_group(klab, la, lb, dims, dims, args.gk, K)) return hipErrorInvalidValue;
   if (flops) *flops += 2.0 * (double)M * (double)N * (double)K;
   if (M == 0 || N == 0) return hipSuccess;
   args.a = A;

@@ -36,11 +36,13 @@ struct LabelDims {
 // error.  `flops` (nullable) is increased by 2*M*N*K.  `scratch` (device,
 // nullable) of scratch_elems doubles lets the engine split long k ranges over
 // several workgroups (partial sums reduced in a fixed order) when the output
-// alone has too few tiles to fill the GPU.
+// alone has too few tiles to fill the GPU.  `cdims` (nullable) gives the leg
+// sizes of the tensor C is a slice of: C's strides come from cdims while the
+// extents of the contraction come from dims (C then points at the slice start).
 hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* la, const void* B,
                     const char* lb, void* C, const char* lc, bool c_f64, double alpha, double beta,
                     hipStream_t stream, double* flops = nullptr, double* scratch = nullptr,
-                    size_t scratch_elems = 0);
+                    size_t scratch_elems = 0, const LabelDims* cdims = nullptr);
 
 // Flop count of the same contraction without launching anything.
 double contract_flops(const LabelDims& dims, const char* la, const char* lb, const char* lc);

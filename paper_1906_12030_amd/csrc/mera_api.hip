@@ -81,7 +81,7 @@ struct Ctx {
 
   // C = alpha * A . B + beta * C   (A, B of the working type; C of the working type or double)
   void c(const void* A, const char* la, const void* B, const char* lb, void* C, const char* lc,
-         bool c_f64, double alpha, double beta) {
+         bool c_f64, double alpha, double beta, const LabelDims* cdims = nullptr) {
     if (dry) {
       flops += mera::contract_flops(dims, la, lb, lc);
       return;
@@ -101,7 +101,7 @@ struct Ctx {
       hipEventRecord(rec.a, s);
     }
     err = mera::contract(ar, dims, A, la, B, lb, C, lc, cf, alpha, beta, s, &flops, scratch,
-                         scratch_elems);
+                         scratch_elems, cdims);
     if (g_prof_on) {
       hipEventRecord(rec.b, s);
       g_prof.push_back(rec);
@@ -168,7 +168,7 @@ struct Pieces {
   void* N;   // [r s b d j]
   void* N3;  // [r b s d j]
   void* M;   // [p q c a j]
-  void* M1;  // [p q c j a]
+  void* M1;  // [q p c j a]
   void* M3;  // [p c q a j]
 };
 
@@ -186,7 +186,7 @@ Pieces build_pieces(Ctx& cx, const LayerT& t, int64_t din, int64_t dout) {
   cx.c(t.w, "bcj", t.u, "rscd", pc.N, "rsbdj", false, 1.0, 0.0);
   cx.c(t.w, "bcj", t.u, "rscd", pc.N3, "rbsdj", false, 1.0, 0.0);
   cx.c(t.u, "pqab", t.w, "bcj", pc.M, "pqcaj", false, 1.0, 0.0);
-  cx.c(t.u, "pqab", t.w, "bcj", pc.M1, "pqcja", false, 1.0, 0.0);
+  cx.c(t.u, "pqab", t.w, "bcj", pc.M1, "qpcja", false, 1.0, 0.0);
   cx.c(t.u, "pqab", t.w, "bcj", pc.M3, "pcqaj", false, 1.0, 0.0);
   return pc;
 }
@@ -203,19 +203,23 @@ struct Bufs {
   void* mid2;  // din^6
 };
 
-Bufs take_bufs(Ctx& cx, int64_t din, int64_t dout) {
+// `rows` = extent of the sliced leading leg (din when not sliced)
+Bufs take_bufs(Ctx& cx, int64_t din, int64_t dout, int64_t rows) {
   Bufs b;
-  b.big = cx.take_t(ipow(din, 6) * dout);
-  b.mid = cx.take_t(ipow(din, 6));
-  b.mid2 = cx.take_t(ipow(din, 6));
+  b.big = cx.take_t(rows * ipow(din, 5) * dout);
+  b.mid = cx.take_t(rows * ipow(din, 5));
+  b.mid2 = cx.take_t(rows * ipow(din, 5));
   return b;
 }
 
 // ---------------------------------------------------------------------------
 // D
 // ---------------------------------------------------------------------------
+// `slices` > 1 processes the left chain in slices of its open leg r (fine
+// site 3) and the right chain in slices of q (fine site 2): the chi^7
+// intermediates then only need 1/slices of their full size.
 int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_out,
-                int placement) {
+                int placement, int slices = 1) {
   const int64_t din = L->din, dout = L->dout;
   set_dims(cx, (int)din, (int)dout);
   LayerT t = working_layer(cx, L);
@@ -223,22 +227,54 @@ int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_
   Pieces pc = build_pieces(cx, t, din, dout);
   void* X1 = cx.take_t(din * din * ipow(dout, 4));
   void* X = cx.take_t(ipow(din, 4) * dout * dout);
-  Bufs b = take_bufs(cx, din, dout);
+  const int64_t R = (din + slices - 1) / slices;
+  Bufs b = take_bufs(cx, din, dout, R);
   build_x(cx, pc, rho, X1, X);
   const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
+  const LabelDims full = cx.dims;
+  const size_t es = cx.elem();
   bool first = true;
   if (placement != MERA_RIGHT) {
-    cx.c(pc.N, "rsbdj", X, "djaADJ", b.big, "rsbaADJ", false, 1.0, 0.0);
-    cx.c(b.big, "rsbaADJ", pc.N, "RsBDJ", b.mid, "rabABR", false, 1.0, 0.0);
-    cx.c(b.mid, "rabABR", t.u, "pqab", b.mid2, "pqrABR", false, 1.0, 0.0);
-    cx.c(b.mid2, "pqrABR", t.u, "PQAB", rho_out, "pqrPQR", true, wgt, 0.0);
+    for (int64_t r0 = 0; r0 < din; r0 += R) {
+      cx.dims = full;
+      cx.dims.d['r'] = std::min(R, din - r0);
+      const char* n_s = static_cast<const char*>(pc.N) + r0 * ipow(din, 3) * dout * es;  // N[r0, ...]
+      cx.c(n_s, "rsbdj", X, "djaADJ", b.big, "rsbaADJ", false, 1.0, 0.0);
+      cx.c(b.big, "rsbaADJ", pc.N, "RsBDJ", b.mid, "rabABR", false, 1.0, 0.0);
+      cx.c(b.mid, "rabABR", t.u, "pqab", b.mid2, "pqrABR", false, 1.0, 0.0);
+      cx.c(b.mid2, "pqrABR", t.u, "PQAB", rho_out + r0 * ipow(din, 3), "pqrPQR", true, wgt, 0.0, &full);
+    }
+    cx.dims = full;
     first = false;
   }
   if (placement != MERA_LEFT) {
-    cx.c(pc.M1, "pqcja", X, "djaADJ", b.big, "pqcdDAJ", false, 1.0, 0.0);
-    cx.c(b.big, "pqcdDAJ", pc.M, "pQCAJ", b.mid, "qcdDCQ", false, 1.0, 0.0);
-    cx.c(b.mid, "qcdDCQ", t.u, "rscd", b.mid2, "qrsCDQ", false, 1.0, 0.0);
-    cx.c(b.mid2, "qrsCDQ", t.u, "RSCD", rho_out, "qrsQRS", true, wgt, first ? 0.0 : 1.0);
+    for (int64_t q0 = 0; q0 < din; q0 += R) {
+      cx.dims = full;
+      cx.dims.d['q'] = std::min(R, din - q0);
+      const char* m_s = static_cast<const char*>(pc.M1) + q0 * ipow(din, 3) * dout * es;  // M1[q0, ...]
+      cx.c(m_s, "qpcja", X, "djaADJ", b.big, "pqcdDAJ", false, 1.0, 0.0);
+      cx.c(b.big, "pqcdDAJ", pc.M, "pQCAJ", b.mid, "qcdDCQ", false, 1.0, 0.0);
+      cx.c(b.mid, "qcdDCQ", t.u, "rscd", b.mid2, "qrsCDQ", false, 1.0, 0.0);
+      cx.c(b.mid2, "qrsCDQ", t.u, "RSCD", rho_out + q0 * ipow(din, 5), "qrsQRS", true, wgt,
+           first ? 0.0 : 1.0, &full);
+    }
+    cx.dims = full;
+  }
+  return 0;
+}
+
+// Smallest slice count whose workspace fits ws_bytes for a body taking the
+// slice count (1 = unsliced); 0 if even one slice per leg value does not fit.
+template <typename Body>
+int choose_slices(const Ctx& proto, int64_t din, size_t ws_bytes, Body&& body) {
+  for (int s = 1; s <= din; ++s) {
+    const int64_t R = (din + s - 1) / s;
+    if (s > 1 && (din + R - 1) / R != s) continue;  // same extent as a smaller count
+    Ctx dry = proto;
+    dry.dry = true;
+    dry.off = 0;
+    body(dry, s);
+    if (dry.off <= ws_bytes) return s;
   }
   return 0;
 }
@@ -254,7 +290,7 @@ int run_ascend(Ctx& cx, const mera_layer* L, const double* h_in, double* h_out, 
   Pieces pc = build_pieces(cx, t, din, dout);
   void* Xb = cx.take_t(ipow(din, 4) * dout * dout);
   void* Z1 = cx.take_t(din * din * ipow(dout, 4));
-  Bufs b = take_bufs(cx, din, dout);
+  Bufs b = take_bufs(cx, din, dout, din);
   const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
   bool first = true;
   if (placement != MERA_RIGHT) {
@@ -290,7 +326,7 @@ int run_env(Ctx& cx, const mera_layer* L, const double* h_in, const double* rho_
   Pieces pc = build_pieces(cx, t, din, dout);
   void* X1 = cx.take_t(din * din * ipow(dout, 4));
   void* X = cx.take_t(ipow(din, 4) * dout * dout);
-  Bufs b = take_bufs(cx, din, dout);
+  Bufs b = take_bufs(cx, din, dout, din);
   void* dN = cx.take_t(ipow(din, 4) * dout);
   void* dM = cx.take_t(ipow(din, 4) * dout);
   void* dX = want_u ? nullptr : cx.take_t(ipow(din, 4) * dout * dout);
@@ -329,7 +365,7 @@ int run_env(Ctx& cx, const mera_layer* L, const double* h_in, const double* rho_
   if (placement != MERA_LEFT) {
     cx.c(h, "QRSqrs", t.u, "RSCD", b.mid2, "qrsCDQ", false, wgt, 0.0);  // H1
     if (want_u) {
-      cx.c(pc.M1, "pqcja", X, "djaADJ", b.big, "pqcdDAJ", false, 1.0, 0.0);
+      cx.c(pc.M1, "qpcja", X, "djaADJ", b.big, "pqcdDAJ", false, 1.0, 0.0);
       cx.c(b.big, "pqcdDAJ", pc.M, "pQCAJ", b.mid, "qcdDCQ", false, 1.0, 0.0);
       acc_env(b.mid2, "qrsCDQ", b.mid, "qcdDCQ", "rscd");
     }
@@ -510,8 +546,15 @@ int mera_descend(const mera_layer* layer, const double* rho_in_d, double* rho_ou
   }
   Ctx cx;
   cx.ar = arith_of(precision);
+  const int S = choose_slices(cx, layer->din, ws_bytes, [&](Ctx& c, int s) {
+    run_descend(c, layer, rho_in_d, rho_out_d, placement, s);
+  });
+  if (S == 0) {
+    set_err("workspace too small even with the chi^7 intermediates sliced");
+    return MERA_EWORKSPACE;
+  }
   return run_checked(cx, ws_d, ws_bytes, hip_stream,
-                     [&](Ctx& c) { run_descend(c, layer, rho_in_d, rho_out_d, placement); });
+                     [&](Ctx& c) { run_descend(c, layer, rho_in_d, rho_out_d, placement, S); });
 }
 
 int mera_ascend(const mera_layer* layer, const double* h_in_d, double* h_out_d, int placement,
@@ -688,6 +731,7 @@ int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int
   // (rho + sum_{k<L} D^k r = D^L rho) while the low-precision products only
   // act on the correction, so their error scales with ||delta||, not ||rho||.
   constexpr int kRefineCycle = 30;
+  int S = 1;  // slices of the chi^7 intermediates (chosen below from ws_bytes)
   auto body = [&](Ctx& c) {
     double* tmp = c.take_d(nn);
     double* prev = resid_d ? c.take_d(nn) : nullptr;
@@ -701,7 +745,7 @@ int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int
       c.off = mark;
       const Arith save = c.ar;
       c.ar = a;
-      run_descend(c, si, in, out, MERA_AVG);
+      run_descend(c, si, in, out, MERA_AVG, S);
       c.ar = save;
     };
     if (c.dry) {  // size the workspace for both arithmetics; count one iteration
@@ -752,6 +796,14 @@ int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int
       }
     }
   };
+  S = choose_slices(cx, d, ws_bytes, [&](Ctx& c, int s) {
+    S = s;
+    body(c);
+  });
+  if (S == 0) {
+    set_err("workspace too small even with the chi^7 intermediates sliced");
+    return MERA_EWORKSPACE;
+  }
   int rc = run_checked(cx, ws_d, ws_bytes, hip_stream, body);
   return rc;
 }
@@ -862,6 +914,40 @@ size_t mera_workspace_bytes(int op, int32_t din, int32_t dout, int precision, in
     default: return 0;
   }
   return cx.off;
+}
+
+size_t mera_workspace_bytes_min(int op, int32_t din, int32_t dout, int precision, int placement) {
+  if (op != MERA_OP_DESCEND && op != MERA_OP_FIXED_POINT)
+    return mera_workspace_bytes(op, din, dout, precision, placement);
+  if (precision < MERA_FP64 || precision > MERA_BF16X3) return 0;
+  if (din < 1 || dout < 1 || (int64_t)dout > (int64_t)din * din) return 0;
+  if (placement < MERA_LEFT || placement > MERA_AVG) return 0;
+  if (op == MERA_OP_FIXED_POINT && din != dout) return 0;
+  mera_layer L{din, dout, reinterpret_cast<const double*>(256), reinterpret_cast<const double*>(256)};
+  const double* dummy = reinterpret_cast<const double*>(256);
+  double* out = reinterpret_cast<double*>(256);
+  Ctx cx;
+  cx.ar = arith_of(precision);
+  cx.dry = true;
+  if (op == MERA_OP_DESCEND) {
+    run_descend(cx, &L, dummy, out, placement, din);
+    return cx.off;
+  }
+  const int64_t n = (int64_t)din * din * din;
+  const bool refine = precision != MERA_FP64;
+  for (int i = 0; i < (refine ? 4 : 2); ++i) cx.take_d(n * n);
+  cx.take_d(mera::kReduceBlocks);
+  cx.take_d(4);
+  const size_t mark = cx.off;
+  cx.ar = Arith::F64;
+  run_descend(cx, &L, dummy, out, MERA_AVG, din);
+  const size_t hi = cx.off;
+  if (refine) {
+    cx.off = mark;
+    cx.ar = arith_of(precision);
+    run_descend(cx, &L, dummy, out, MERA_AVG, din);
+  }
+  return std::max(hi, cx.off);
 }
 
 double mera_flops(int op, int32_t din, int32_t dout, int placement) {

@@ -1,0 +1,141 @@
+"""Command-line driver: optimise a scale-invariant binary MERA for the critical Ising chain.
+
+    python -m paper_1906_12030_amd.run --chi 8 --layers 3 --sweeps 500 --precision fp64 \
+        [--seed 0] [--iters 30] [--save state.npz] [--resume state.npz] [--grow-from small.npz]
+        [--dims 12] [--log run.jsonl]
+
+Prints one JSON line per reporting interval (energy per site, error against
+the exact -4/pi of Sec. III.A, seconds per sweep) and, with --dims k, the k
+lowest scaling dimensions of the final scale-invariant layer (Sec. III.A).
+Checkpoints hold every tensor, rho*, the sweep index and the settings; a
+resumed run continues the same trajectory.  --grow-from pads a converged
+smaller-chi state to --chi (zero padding of every leg, seeded N(0, 1e-3)
+noise, re-projection onto isometries) as a warm start.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import inputs, ops, scaling, sweep
+
+EXACT = -4.0 / math.pi
+
+
+def save_state(path, m: sweep.GpuMera, meta: dict):
+    st = m.state_dict()
+    arrays = {"rho_star": st["rho_star"], "si_u": st["si"][0], "si_w": st["si"][1]}
+    for t, (u, w) in enumerate(st["layers"]):
+        arrays[f"u{t}"] = u
+        arrays[f"w{t}"] = w
+    np.savez(path, meta=json.dumps(meta), **arrays)
+
+
+def load_state(path, device="cuda"):
+    z = np.load(path, allow_pickle=False)
+    meta = json.loads(str(z["meta"]))
+    T = sum(1 for k in z.files if k.startswith("u"))
+    layers = [(z[f"u{t}"], z[f"w{t}"]) for t in range(T)]
+    return sweep.GpuMera(layers, (z["si_u"], z["si_w"]), z["rho_star"], device), meta
+
+
+def _project(mat):
+    q, r = np.linalg.qr(mat)
+    return q * np.sign(np.where(np.diag(r) == 0, 1.0, np.diag(r)))[None, :]
+
+
+def _polar(mat):
+    uu, _, vt = np.linalg.svd(mat, full_matrices=False)
+    return uu @ vt
+
+
+def grow(small_layers, small_si, chi, n_transitional, seed, noise=1e-3):
+    """Pad a smaller state to bond dimension chi: zero-pad legs, add seeded noise, re-project.
+
+    Layers beyond the small state's depth copy the small state's scale-invariant tensors.
+    """
+    rng = np.random.default_rng(seed)
+    dims = inputs.bond_dims(chi, n_transitional)
+    src = list(small_layers) + [small_si] * (n_transitional - len(small_layers))
+    out = []
+    for t in range(n_transitional + 1):
+        din = dims[t] if t < n_transitional else dims[-1]
+        dout = dims[t + 1] if t < n_transitional else dims[-1]
+        u0, w0 = src[t] if t < n_transitional else small_si
+        u = np.zeros((din,) * 4)
+        w = np.zeros((din, din, dout))
+        a, b = min(din, u0.shape[0]), min(dout, w0.shape[2])
+        u[:a, :a, :a, :a] = u0[:a, :a, :a, :a]
+        w[:a, :a, :b] = w0[:a, :a, :b]
+        u += noise * rng.standard_normal(u.shape)
+        w += noise * rng.standard_normal(w.shape)
+        u = _polar(u.reshape(din * din, din * din)).reshape(u.shape)
+        w = _polar(w.reshape(din * din, dout)).reshape(w.shape)
+        out.append((u, w))
+    return out[:-1], out[-1]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--chi", type=int, default=8)
+    ap.add_argument("--layers", type=int, default=3)
+    ap.add_argument("--sweeps", type=int, default=100)
+    ap.add_argument("--iters", type=int, default=30)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--si-levels", type=int, default=1)
+    ap.add_argument("--every", type=int, default=10)
+    ap.add_argument("--save", default=None)
+    ap.add_argument("--resume", default=None)
+    ap.add_argument("--grow-from", default=None)
+    ap.add_argument("--dims", type=int, default=0)
+    ap.add_argument("--log", default=None)
+    a = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        raise SystemExit("a GPU is required")
+    start = 0
+    if a.resume:
+        m, meta = load_state(a.resume)
+        start = int(meta.get("sweep", 0))
+    elif a.grow_from:
+        small, _ = load_state(a.grow_from)
+        st = small.state_dict()
+        layers, si = grow(st["layers"], st["si"], a.chi, a.layers, a.seed)
+        m = sweep.GpuMera(layers, si)
+    else:
+        m = sweep.GpuMera.seeded(a.chi, a.layers, a.seed)
+    h1, shift = ops.tfim_hamiltonian(1.0)
+    if not a.resume:
+        sweep.initial_fixed_point(m, a.iters, a.precision)
+    log = open(a.log, "a") if a.log else None
+    t0 = time.perf_counter()
+    e = float("nan")
+    for k in range(start, start + a.sweeps):
+        ek, c = sweep.sweep(m, h1, shift, a.iters, a.precision, a.si_levels)
+        if (k + 1) % a.every == 0 or k + 1 == start + a.sweeps:
+            e = float(ek.item()) + c
+            dt = (time.perf_counter() - t0) / (k + 1 - start)
+            rec = {"sweep": k + 1, "energy": e, "rel_error": (e - EXACT) / abs(EXACT), "s_per_sweep": dt,
+                   "chi": a.chi, "precision": a.precision}
+            line = json.dumps(rec)
+            print(line, flush=True)
+            if log:
+                log.write(line + "\n")
+                log.flush()
+    if a.save:
+        save_state(a.save, m, {"sweep": start + a.sweeps, "chi": a.chi, "layers": a.layers,
+                               "seed": a.seed, "iters": a.iters, "precision": a.precision})
+    if a.dims > 0:
+        d, lam, calls = scaling.scaling_dimensions(m.si[0], m.si[1], k=a.dims)
+        print(json.dumps({"scaling_dimensions": [round(float(x), 6) for x in d], "matvecs": calls}), flush=True)
+    return e
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -65,8 +65,14 @@ def test_invalid_arguments_rejected_before_device(lib):
 def test_workspace_too_small_and_misaligned(lib):
     fake = 4096
     need = _lib.mera_workspace_bytes(_lib.MERA_OP_DESCEND, 4, 4, 0, 2)
-    assert need > 0
-    assert _lib.mera_descend(_layer(4, 4), fake, fake, 2, 0, fake, need - 1, None) == _lib.MERA_EWORKSPACE
+    least = _lib.mera_workspace_bytes_min(_lib.MERA_OP_DESCEND, 4, 4, 0, 2)
+    assert 0 < least < need
+    assert _lib.mera_descend(_layer(4, 4), fake, fake, 2, 0, fake, least - 1, None) == _lib.MERA_EWORKSPACE
+    assert _lib.mera_env_u(_layer(4, 4), fake, fake, fake, 2, 0, fake, 1024, None) == _lib.MERA_EWORKSPACE
+    fneed = _lib.mera_workspace_bytes_min(_lib.MERA_OP_FIXED_POINT, 4, 4, 2, 2)
+    assert 0 < fneed < _lib.mera_workspace_bytes(_lib.MERA_OP_FIXED_POINT, 4, 4, 2, 2)
+    # far below the sliced minimum: rejected before any device work
+    assert _lib.mera_fixed_point_rho(_layer(4, 4), fake, 3, 2, None, fake, fneed // 4, None) == _lib.MERA_EWORKSPACE
     assert _lib.mera_descend(_layer(4, 4), fake, fake, 2, 0, fake + 8, need, None) == _lib.MERA_EINVAL
     npol = _lib.mera_workspace_bytes(_lib.MERA_OP_POLAR, 16, 4, 0, 0)
     st, _ = _lib.mera_polar_update(fake, 16, 4, fake, fake, npol - 1, None)
@@ -85,6 +91,18 @@ def test_workspace_grows_with_bond_dimension(lib):
     assert 0.45 < ws32 / ws < 0.6
     assert _lib.mera_workspace_bytes(_lib.MERA_OP_DESCEND, 4, 17, 0, 2) == 0
     assert _lib.mera_workspace_bytes(99, 4, 4, 0, 2) == 0
+
+
+def test_sliced_workspace_shrinks_as_chi7_over_slices(lib):
+    """Slicing the chi^7 intermediates over an open leg: the minimum workspace drops by ~chi."""
+    for prec, es in ((0, 8), (2, 4)):
+        full = _lib.mera_workspace_bytes(_lib.MERA_OP_DESCEND, 24, 24, prec, 2)
+        least = _lib.mera_workspace_bytes_min(_lib.MERA_OP_DESCEND, 24, 24, prec, 2)
+        assert full - least > 0.9 * (24 ** 7 - 24 ** 6) * es
+    # chi=32 in split bf16 fits a 288 GB device only when sliced for the FP64 refinement
+    fp = _lib.mera_workspace_bytes(_lib.MERA_OP_FIXED_POINT, 32, 32, 2, 2)
+    fp_min = _lib.mera_workspace_bytes_min(_lib.MERA_OP_FIXED_POINT, 32, 32, 2, 2)
+    assert fp > 288e9 > 2 * fp_min
 
 
 def test_flop_accounting_scales_as_chi9(lib):

@@ -185,3 +185,40 @@ def test_refined_fixed_point_reaches_fp64_fixed_point(ops, prec):
     assert rel(host(r64), ref) < 1e-12
     # plain low-precision power iteration stalls near 1e-6; the refined one does not
     assert rel(host(rlp), ref) < 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_sliced_descend_matches_unsliced(ops, prec):
+    """With the minimum workspace the chi^7 intermediates are sliced over an open leg."""
+    from paper_1906_12030_amd import _lib
+    din, dout = 8, 8
+    u, w, rho, h = _case(din, dout, 5)
+    say(f"sliced descend {prec}")
+    layer = ops.Layer(gpu(u), gpu(w))
+    full = host(ops.descend(layer, gpu(rho), "AVG", prec))
+    q = ops.PRECISIONS[prec]
+    nb = _lib.mera_workspace_bytes_min(_lib.MERA_OP_DESCEND, din, dout, q, _lib.MERA_AVG)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    base = (ws.data_ptr() + 255) & ~255
+    out = torch.empty((din,) * 6, dtype=torch.float64, device="cuda")
+    r = gpu(rho)
+    st = _lib.mera_descend(layer.c(), r.data_ptr(), out.data_ptr(), _lib.MERA_AVG, q, base, nb,
+                           torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    sliced = host(out)
+    # different slice shapes change the split-bf16 summation order, not the accuracy
+    assert rel(sliced, full) < (1e-14 if prec == "fp64" else 1e-5)
+    assert rel(sliced, O.descend(u, w, rho)) < TOL[prec]
+    # fixed point with its minimum workspace (sliced FP64 refinement residual)
+    nf = _lib.mera_workspace_bytes_min(_lib.MERA_OP_FIXED_POINT, din, dout, q, _lib.MERA_AVG)
+    ws2 = torch.empty(nf + 256, dtype=torch.uint8, device="cuda")
+    base2 = (ws2.data_ptr() + 255) & ~255
+    r1 = gpu(O.identity_density(din))
+    r2 = gpu(O.identity_density(din))
+    ops.fixed_point_rho(layer, r1, 12, prec)
+    st = _lib.mera_fixed_point_rho(layer.c(), r2.data_ptr(), 12, q, None, base2, nf,
+                                   torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    # same algorithm, different slice shapes: equal up to the reduced-precision rounding of the
+    # correction (far from convergence after 12 steps the correction is not small)
+    assert rel(host(r2), host(r1)) < (1e-14 if prec == "fp64" else 1e-5)

@@ -67,3 +67,22 @@ def test_mixed_precision_sweep_close_to_fp64(mods):
     print(es, file=sys.stderr, flush=True)
     assert abs(es["fp32"] - es["fp64"]) < 1e-4
     assert abs(es["bf16x3"] - es["fp64"]) < 1e-3
+
+
+def test_checkpoint_resume_reproduces_trajectory(mods, tmp_path):
+    """Save after two sweeps, reload, continue: bitwise the same energies as an uninterrupted run."""
+    ops, sweep = mods
+    from paper_1906_12030_amd import run
+    h, c = ops.tfim_hamiltonian(1.0)
+    a = sweep.GpuMera.seeded(6, 2, 3)
+    sweep.initial_fixed_point(a, 30)
+    e_a = [float(sweep.sweep(a, h, c, 30)[0].item()) for _ in range(4)]
+    b = sweep.GpuMera.seeded(6, 2, 3)
+    sweep.initial_fixed_point(b, 30)
+    e_b = [float(sweep.sweep(b, h, c, 30)[0].item()) for _ in range(2)]
+    path = str(tmp_path / "ckpt.npz")
+    run.save_state(path, b, {"sweep": 2})
+    b2, meta = run.load_state(path)
+    assert meta["sweep"] == 2
+    e_b += [float(sweep.sweep(b2, h, c, 30)[0].item()) for _ in range(2)]
+    assert e_a == e_b
