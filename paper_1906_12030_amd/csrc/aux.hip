@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "engine.h"
+#include "tc_common.h"
 
 namespace mera {
 
@@ -21,6 +22,12 @@ __global__ void k_to_f32(const double* __restrict__ x, float* __restrict__ y, in
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (float)x[i];
+}
+
+__global__ void k_to_split(const double* __restrict__ x, uint32_t* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = pack_split((float)x[i]);
 }
 
 __global__ void k_scale(const double* __restrict__ x, double* __restrict__ y, double a, int64_t n) {
@@ -151,8 +158,12 @@ hipError_t launch_sqrt_ratio(const double* a, const double* b, double* out, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
+hipError_t launch_to_f32(const double* x, float* y, int64_t n, bool split, hipStream_t s) {
+  if (split)
+    hipLaunchKernelGGL(k_to_split, dim3(grid_for(n)), dim3(kBlock), 0, s, x,
+                       reinterpret_cast<uint32_t*>(y), n);
+  else
+    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
   return hipGetLastError();
 }
 hipError_t launch_scale(const double* x, double* y, double a, int64_t n, hipStream_t s) {

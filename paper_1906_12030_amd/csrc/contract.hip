@@ -177,8 +177,8 @@ __global__ __launch_bounds__(256) void tc_splitk_reduce(TcArgs p) {
     const uint32_t m = (uint32_t)(t / p.N), n = (uint32_t)(t - (int64_t)m * p.N);
     TC* dst = static_cast<TC*>(p.c) + goff<true>(p.gm, m) + goff<true>(p.gn, n);
     double y = p.alpha * s;
-    if (p.beta != 0.0) y += p.beta * (double)(*dst);
-    *dst = (TC)y;
+    if (p.beta != 0.0) y += p.beta * load_c(p, dst);
+    *dst = store_c<TC>(p, y);
   }
 }
 
@@ -365,6 +365,8 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
   args.K = (int32_t)K;
   args.alpha = alpha;
   args.beta = beta;
+  // the split-bf16 path keeps its FP32 intermediates as split words
+  args.csplit = (ar == Arith::B3 && !c_f64) ? 1 : 0;
   // loader modes: contiguous leg of A along k (else along m); of B along n (else along k)
   const bool akc = a_last_k && args.gk.sx[args.gk.nd - 1] == 1;
   const bool amc = a_last_m && args.gm.sx[args.gm.nd - 1] == 1;
@@ -384,16 +386,23 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
   const int bk = (ar == Arith::B3) ? 32 : 16;
   const bool kal = args.gk.size[args.gk.nd - 1] % bk == 0;
   if (!kal) va = vb = false;
-  args.tiles_m = (int32_t)((M + kBM - 1) / kBM);
-  args.tiles_n = (int32_t)((N + kBN - 1) / kBN);
+  // Split-bf16 contractions whose operands are both contiguous along k go to
+  // the large-tile kernel with direct-to-LDS loads (contract_b3x.hip).
+  int xbn = 0;
+  const bool use_x = ar == Arith::B3 && kal && akc && va && bkc && !bnc && vb &&
+                     contract_b3x_fits(M, N, xbn);
+  const int64_t tbm = use_x ? 256 : kBM, tbn = use_x ? xbn : kBN;
+  args.tiles_m = (int32_t)((M + tbm - 1) / tbm);
+  args.tiles_n = (int32_t)((N + tbn - 1) / tbn);
   const int64_t tiles = (int64_t)args.tiles_m * args.tiles_n;
   // Split k when the output has too few tiles to fill the GPU (two resident
-  // workgroups on each of the 256 CUs): pick the split count that best fills
-  // whole waves of workgroups, with at least 8 k-tiles per split.
+  // workgroups on each of the 256 CUs; one for the large-tile kernel): pick
+  // the split count that best fills whole waves of workgroups, with at least
+  // 8 k-tiles per split.
   int splits = 1;
   int64_t kchunk = ((K + bk - 1) / bk) * bk;
   if (scratch && scratch_elems > 0) {
-    constexpr double kSlots = 512.0;
+    const double kSlots = use_x ? 256.0 : 512.0;
     auto fill = [&](int64_t n) { return (double)n / (std::ceil((double)n / kSlots) * kSlots); };
     double best = fill(tiles);
     for (int s = 2; s <= 16; ++s) {
@@ -430,6 +439,8 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
   } else if (ar == Arith::F32) {
     e = c64 ? dispatch<float, double>(args, blocks, A_KC, va, B_NC, vb, kal, stream)
             : dispatch<float, float>(args, blocks, A_KC, va, B_NC, vb, kal, stream);
+  } else if (use_x) {
+    e = launch_contract_b3x(args, xbn, c64, stream);
   } else {
     e = launch_contract_b3(args, A_KC, va, B_NC, vb, kal, c64, stream);
   }

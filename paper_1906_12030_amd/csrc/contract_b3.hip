@@ -1,13 +1,17 @@
 // Split-bf16 ("3xBF16") contraction kernel for gfx950.
 //
-// Operands arrive as FP32.  On the way into LDS every value x is split into
+// Every FP32 value x is represented by two bf16 numbers,
 //   hi = bf16_rne(x),  lo = bf16_rne(x - hi),
 // and the tile product is formed on BF16 MFMA (v_mfma_f32_16x16x32_bf16) as
 //   hi_a*hi_b + hi_a*lo_b + lo_a*hi_b      (lo*lo, of relative size 2^-16, is dropped)
 // with FP32 accumulation (Henry, Tang and Heinecke, "Leveraging the bfloat16
 // artificial intelligence datatype for higher-precision computations",
-// ARITH 2019).  The addressing (separable leg offsets, XCD-aware tile order)
-// is the same as in the FP64/FP32 kernel of contract.hip.
+// ARITH 2019).  Operands and FP32 results are kept in HBM as split words
+// (hi in the upper, lo in the lower half of a 4-byte element; see
+// pack_split), so the split is done once, by the producer of a tensor, and
+// the loaders here only regroup halves: one v_perm per element on the way
+// into LDS.  The addressing (separable leg offsets, XCD-aware tile order) is
+// the same as in the FP64/FP32 kernel of contract.hip.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -21,31 +25,50 @@ namespace b3 {
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u2_t __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
+// hi (lo) halves of two consecutive-k split words, first word in the low half
+__device__ __forceinline__ uint32_t hi_pair(float a, float b) {
+  return __builtin_amdgcn_perm(__float_as_uint(b), __float_as_uint(a), 0x07060302u);
+}
+__device__ __forceinline__ uint32_t lo_pair(float a, float b) {
+  return __builtin_amdgcn_perm(__float_as_uint(b), __float_as_uint(a), 0x05040100u);
 }
 
 constexpr int kBM = 128;
 constexpr int kBN = 128;
 constexpr int kBK = 32;
-constexpr int kPadK = 8;  // bf16 elements of padding per LDS row (keeps 16-lane b128 reads conflict-free)
 
-constexpr int kRow = kBK + kPadK;
+// LDS tile of one operand: kBM rows of 128 bytes, i.e. eight 16-byte slots,
+// logical slots 0..3 = hi of k 0-7, 8-15, 16-23, 24-31 and 4..7 = lo of the
+// same.  Logical slot s of row r sits at physical slot s ^ swz(r).  gfx950's
+// LDS serves a 16-byte-per-lane access without conflicts when each half-wave
+// (32 lanes) touches 32 distinct 16-byte slots modulo 512 bytes; with
+// swz(r) = rotate-left of the 3 bits ((r >> 2) & 7) that holds for the MFMA
+// fragment reads (16 rows x 2 k-slots per half-wave), for the row loader's
+// writes (32 consecutive rows at one slot) and for TileLoad's 8-byte writes
+// (4 rows x 128 bytes).
+constexpr int kRowBytes = 128;
+constexpr int kTileBytes = kBM * kRowBytes;
 
-// Operand loaders for the split kernel.  LDS holds each operand as
-// [row][k] (k fastest) so that an MFMA fragment (8 consecutive k of one row)
-// is one 16-byte read.  KC operands (contiguous along k) use TileLoad; operands
-// contiguous along their rows (m for A, n for B) are read 16 k per thread at
-// one row, so that every global load of a wave covers 64 consecutive rows and
-// every LDS write is a 16-byte row segment.
+__device__ __forceinline__ int swz(int r) { return (((r >> 2) & 3) << 1) | ((r >> 4) & 1); }
+// byte offset of logical slot s of row r
+__device__ __forceinline__ int slot_off(int r, int s) { return r * kRowBytes + ((s ^ swz(r)) << 4); }
+
+// Operand loaders for the split kernel.  KC operands (contiguous along k)
+// use TileLoad (V consecutive k of one row per thread); operands contiguous
+// along their rows (m for A, n for B) are read 16 k per thread at one row, so
+// that every global load of a wave covers 64 consecutive rows and every LDS
+// write is a 16-byte slot.  The store regroups the split words' halves into
+// the hi and lo slots (one v_perm per element).
 template <bool KC, int V, bool KAL, bool KSecond>
 struct B3Load;
 
 template <int V, bool KAL, bool KSecond>
 struct B3Load<true, V, KAL, KSecond> {
-  TileLoad<float, 128, kBK, true, V, KAL, KSecond> t;
+  using TL = TileLoad<float, 128, kBK, true, V, KAL, KSecond>;
+  TL t;
   __device__ __forceinline__ void init(const Group& grow, const Group& gk, uint32_t row0,
                                        uint32_t nrows) {
     t.init(grow, gk, row0, nrows);
@@ -57,16 +80,34 @@ struct B3Load<true, V, KAL, KSecond> {
                                        uint32_t kend) {
     t.load(base, gk, k0, kend);
   }
-  __device__ __forceinline__ void store(__bf16 (*H)[kRow], __bf16 (*L)[kRow]) {
+  __device__ __forceinline__ void store(char* T) {
+    const int s = t.vec >> 3;       // k-slot of this thread's k
+    const int b = (t.vec & 7) * 2;  // byte offset inside the slot
+    // passes step by LPP rows; with LPP a multiple of 32 the swizzle (bits
+    // 2..4 of the row) is the same in every pass
+    const int oh = slot_off(t.line, s) + b, ol = slot_off(t.line, 4 + s) + b;
 #pragma unroll
-    for (int i = 0; i < t.NP; ++i)
+    for (int i = 0; i < TL::NP; ++i) {
+      const int r = t.line + i * TL::LPP;
+      const float* x = t.r[i];
+      if constexpr (V == 4 && TL::LPP % 32 == 0) {
+        *reinterpret_cast<u2_t*>(T + oh + i * TL::LPP * kRowBytes) =
+            u2_t{hi_pair(x[0], x[1]), hi_pair(x[2], x[3])};
+        *reinterpret_cast<u2_t*>(T + ol + i * TL::LPP * kRowBytes) =
+            u2_t{lo_pair(x[0], x[1]), lo_pair(x[2], x[3])};
+      } else if constexpr (V == 4) {
+        *reinterpret_cast<u2_t*>(T + slot_off(r, s) + b) = u2_t{hi_pair(x[0], x[1]), hi_pair(x[2], x[3])};
+        *reinterpret_cast<u2_t*>(T + slot_off(r, 4 + s) + b) =
+            u2_t{lo_pair(x[0], x[1]), lo_pair(x[2], x[3])};
+      } else {
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        __bf16 h, l;
-        split_bf16(t.r[i][v], h, l);
-        H[t.line + i * t.LPP][t.vec + v] = h;
-        L[t.line + i * t.LPP][t.vec + v] = l;
+        for (int v = 0; v < V; ++v) {
+          const uint32_t w = __float_as_uint(x[v]);
+          *reinterpret_cast<uint16_t*>(T + slot_off(r, s) + b + 2 * v) = (uint16_t)(w >> 16);
+          *reinterpret_cast<uint16_t*>(T + slot_off(r, 4 + s) + b + 2 * v) = (uint16_t)(w & 0xffffu);
+        }
       }
+    }
   }
 };
 
@@ -98,33 +139,28 @@ struct B3Load<false, V, KAL, KSecond> {
       r[e] = k < kend ? base[roff + goff<KSecond>(gk, k)] : 0.f;
     }
   }
-  __device__ __forceinline__ void store(__bf16 (*H)[kRow], __bf16 (*L)[kRow]) {
-    bf8_t h0, h1, l0, l1;
+  __device__ __forceinline__ void store(char* T) {
+    u4_t h0, h1, l0, l1;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      __bf16 h, l;
-      split_bf16(r[e], h, l);
-      h0[e] = h;
-      l0[e] = l;
-      split_bf16(r[e + 8], h, l);
-      h1[e] = h;
-      l1[e] = l;
+    for (int e = 0; e < 4; ++e) {
+      h0[e] = hi_pair(r[2 * e], r[2 * e + 1]);
+      l0[e] = lo_pair(r[2 * e], r[2 * e + 1]);
+      h1[e] = hi_pair(r[8 + 2 * e], r[8 + 2 * e + 1]);
+      l1[e] = lo_pair(r[8 + 2 * e], r[8 + 2 * e + 1]);
     }
-    *reinterpret_cast<bf8_t*>(&H[row][kg * 16]) = h0;
-    *reinterpret_cast<bf8_t*>(&H[row][kg * 16 + 8]) = h1;
-    *reinterpret_cast<bf8_t*>(&L[row][kg * 16]) = l0;
-    *reinterpret_cast<bf8_t*>(&L[row][kg * 16 + 8]) = l1;
+    *reinterpret_cast<u4_t*>(T + slot_off(row, 2 * kg)) = h0;
+    *reinterpret_cast<u4_t*>(T + slot_off(row, 2 * kg + 1)) = h1;
+    *reinterpret_cast<u4_t*>(T + slot_off(row, 4 + 2 * kg)) = l0;
+    *reinterpret_cast<u4_t*>(T + slot_off(row, 5 + 2 * kg)) = l1;
   }
 };
 
 template <typename TC, bool A_KC, int VA, bool B_NC, int VB, bool KAL>
 __global__ __launch_bounds__(kThreads) void tc_b3_kernel(TcArgs p) {
-  __shared__ __attribute__((aligned(16))) char smem[2 * (kBM + kBN) * kRow * sizeof(__bf16)];
-  __bf16 (*Ah)[kRow] = reinterpret_cast<__bf16 (*)[kRow]>(smem);
-  __bf16 (*Al)[kRow] = reinterpret_cast<__bf16 (*)[kRow]>(smem + kBM * kRow * sizeof(__bf16));
-  __bf16 (*Bh)[kRow] = reinterpret_cast<__bf16 (*)[kRow]>(smem + 2 * kBM * kRow * sizeof(__bf16));
-  __bf16 (*Bl)[kRow] =
-      reinterpret_cast<__bf16 (*)[kRow]>(smem + (2 * kBM + kBN) * kRow * sizeof(__bf16));
+  static_assert(kBM == kBN, "one tile geometry for both operands");
+  __shared__ __attribute__((aligned(16))) char smem[2 * kTileBytes];
+  char* As = smem;
+  char* Bs = smem + kTileBytes;
 
   int tm, tn, split;
   if (!tile_of_block(p, tm, tn, split)) return;
@@ -145,11 +181,6 @@ __global__ __launch_bounds__(kThreads) void tc_b3_kernel(TcArgs p) {
   la.init(p.gm, p.gk, m0, (uint32_t)p.M);
   lb.init(p.gn, p.gk, n0, (uint32_t)p.N);
 
-  auto store_tiles = [&]() {
-    la.store(Ah, Al);
-    lb.store(Bh, Bl);
-  };
-
   f4_t acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -158,7 +189,13 @@ __global__ __launch_bounds__(kThreads) void tc_b3_kernel(TcArgs p) {
 
   const int nk = (int)((kend - kbeg + kBK - 1) / kBK);
   const int lr = lane & 15;
-  const int lk = (lane >> 4) * 8;
+  // Fragment rows are wm + 16 i + lr (wn + 16 j + lr): their swizzle is
+  // ((lr >> 2) & 3) << 1 with bit 0 = parity of the block, so the byte
+  // offsets are a per-lane base, the block's 2 KB step and one of four slot
+  // offsets (hi / lo, even / odd block).
+  const int x0 = ((lane >> 4) ^ (((lr >> 2) & 3) << 1)) << 4;  // hi slot, even block
+  const int xo[4] = {x0, x0 ^ 16, x0 ^ 64, x0 ^ 80};          // hi even/odd, lo even/odd
+  const int abase = (wm + lr) * kRowBytes, bbase = (wn + lr) * kRowBytes;
   KWalk<kBK> kw;
   if constexpr (KAL) kw.init(p.gk, kbeg);
   // k-tile fetch: carry walk for k-aligned tiles, leg decomposition otherwise
@@ -174,21 +211,20 @@ __global__ __launch_bounds__(kThreads) void tc_b3_kernel(TcArgs p) {
   };
   fetch(0);
   for (int kt = 0; kt < nk; ++kt) {
-    store_tiles();
+    la.store(As);
+    lb.store(Bs);
     __syncthreads();
-    if (kt + 1 < nk) {
-      fetch(kt + 1);
-    }
+    if (kt + 1 < nk) fetch(kt + 1);
     bf8_t ah[4], al[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      ah[i] = *reinterpret_cast<const bf8_t*>(&Ah[wm + i * 16 + lr][lk]);
-      al[i] = *reinterpret_cast<const bf8_t*>(&Al[wm + i * 16 + lr][lk]);
+      ah[i] = *reinterpret_cast<const bf8_t*>(As + abase + xo[i & 1] + i * 16 * kRowBytes);
+      al[i] = *reinterpret_cast<const bf8_t*>(As + abase + xo[2 + (i & 1)] + i * 16 * kRowBytes);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const bf8_t bh = *reinterpret_cast<const bf8_t*>(&Bh[wn + j * 16 + lr][lk]);
-      const bf8_t bl = *reinterpret_cast<const bf8_t*>(&Bl[wn + j * 16 + lr][lk]);
+      const bf8_t bh = *reinterpret_cast<const bf8_t*>(Bs + bbase + xo[j & 1] + j * 16 * kRowBytes);
+      const bf8_t bl = *reinterpret_cast<const bf8_t*>(Bs + bbase + xo[2 + (j & 1)] + j * 16 * kRowBytes);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);

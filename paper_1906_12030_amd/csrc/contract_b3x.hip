@@ -1,0 +1,315 @@
+// Large-tile split-bf16 contraction kernel for gfx950 (operands contiguous
+// along k).
+//
+// Same arithmetic as contract_b3.hip (split words hi|lo, three BF16 MFMA
+// products per multiply-add, FP32 accumulation), organised for the long
+// chi^9 contractions whose k-tiles both operands store contiguously:
+//   * 256 x BN output tile (BN = 256 or 192), 512 threads = 8 waves in a
+//     2 (m) x 4 (n) grid, each wave 128 x BN/4 on v_mfma_f32_16x16x32_bf16;
+//     twice the tile edge of the 128 x 128 kernel halves the bytes that
+//     have to come through L2 per flop;
+//   * operand k-tiles (32 split words per row) go straight from global
+//     memory into LDS with global_load_lds_dwordx4, in a two-stage ring:
+//     the loads of tile kt+1 fly while the MFMAs of tile kt run, and no
+//     registers are spent on staging;
+//   * LDS rows are 128 bytes (eight 16-byte slots of 4 k each); slot s of
+//     row r is stored at s ^ swz(r) so that the fragment reads of a
+//     half-wave (16 rows x 2 slots) hit 32 distinct 16-byte slots modulo
+//     512 bytes (conflict-free on gfx950's LDS);
+//   * each lane reads its 8 consecutive k of a row as two 16-byte slots
+//     and regroups the halves into the hi and lo MFMA operands (v_perm).
+#include <hip/hip_runtime.h>
+
+#include "engine.h"
+#include "tc_common.h"
+
+namespace mera {
+
+namespace b3x {
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kThreadsX = 512;
+constexpr int kBM = 256;
+constexpr int kBK = 32;
+constexpr int kRowBytes = kBK * 4;  // one row of a k-tile: 32 split words
+
+// slot swizzle: bits 2 and 3 of the row select bits 0 and 2 of the slot
+__device__ __forceinline__ int swz(int r) { return ((r >> 2) & 1) | (((r >> 3) & 1) << 2); }
+
+__device__ __forceinline__ uint32_t hi_pair(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_perm(b, a, 0x07060302u);
+}
+__device__ __forceinline__ uint32_t lo_pair(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_perm(b, a, 0x05040100u);
+}
+
+// Workgroup barrier without the memory fence of __syncthreads(): that fence
+// would wait for every LDS-DMA load of the wave (vmcnt(0)), including the
+// ones of the next k-tile; the loop orders LDS itself (wait_vmcnt before the
+// barrier that publishes a stage, MFMA operands consumed before the barrier
+// that frees it).  The empty asm keeps the compiler from moving memory
+// accesses across the barrier.
+__device__ __forceinline__ void barrier_nofence() {
+  __asm__ volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
+}
+
+// Wait until at most n vector-memory operations of this wave are in flight
+// (s_waitcnt with the expcnt and lgkmcnt fields at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+template <int BN>
+struct Geo {
+  static constexpr int kWNB = BN / 64;  // 16-column blocks of a wave (4 waves along n)
+  static constexpr int kWN = BN / 4;    // columns of a wave
+  static constexpr int kATile = kBM * kRowBytes;
+  static constexpr int kBTile = BN * kRowBytes;
+  static constexpr int kStage = kATile + kBTile;
+  static constexpr int kAIns = kBM / 64;  // 1 KB (8-row) DMA chunks per wave for A
+  static constexpr int kBIns = BN / 64;   // and for B
+  static constexpr int kIns = kAIns + kBIns;
+  static_assert(BN % 64 == 0 && BN <= 256, "tile width");
+};
+
+// LDS bytes of the kernel: two stages, reused by the epilogue.
+template <int BN>
+constexpr int lds_bytes() {
+  return 2 * Geo<BN>::kStage;
+}
+
+// Epilogue: each wave parks one 16-row group of its accumulators in LDS and
+// re-reads it so that every lane stores 16 contiguous bytes.
+template <typename TC, int BN>
+__device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[8][Geo<BN>::kWNB],
+                                             uint32_t m0, uint32_t n0, int split, char* lds,
+                                             int wm, int wn) {
+  using G = Geo<BN>;
+  constexpr int LD = G::kWN + 4;  // floats per staged row (pad keeps 16-byte alignment)
+  int64_t* rows = reinterpret_cast<int64_t*>(lds);
+  int64_t* cols = rows + kBM;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  float* st = reinterpret_cast<float*>(lds + (kBM + BN) * 8) + wave * 16 * LD;
+  for (int i = tid; i < kBM + BN; i += kThreadsX) {
+    if (i < kBM) {
+      const uint32_t m = m0 + i;
+      int64_t o = -1;
+      if (m < (uint32_t)p.M) o = p.splits > 1 ? ((int64_t)split * p.M + m) * p.N : goff<true>(p.gm, m);
+      rows[i] = o;
+    } else {
+      const uint32_t n = n0 + (i - kBM);
+      int64_t o = -1;
+      if (n < (uint32_t)p.N) o = p.splits > 1 ? (int64_t)n : goff<true>(p.gn, n);
+      cols[i - kBM] = o;
+    }
+  }
+  TC* __restrict__ C = p.splits > 1 ? reinterpret_cast<TC*>(p.part) : static_cast<TC*>(p.c);
+  const double alpha = p.splits > 1 ? 1.0 : p.alpha;
+  const double beta = p.splits > 1 ? 0.0 : p.beta;
+  const bool vec = p.cvec != 0;
+  constexpr int PER_ROW = G::kWN / 4;       // 16-byte vectors per staged row
+  constexpr int ITER = 16 * PER_ROW / 64;   // vectors per lane
+  static_assert(16 * PER_ROW % 64 == 0, "epilogue geometry");
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    __syncthreads();  // offsets staged / previous row group consumed
+#pragma unroll
+    for (int j = 0; j < G::kWNB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) st[(4 * (lane >> 4) + r) * LD + j * 16 + (lane & 15)] = acc[i][j][r];
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int idx = it * 64 + lane;
+      const int row = idx / PER_ROW;
+      const int col = (idx % PER_ROW) * 4;
+      const int64_t ro = rows[wm + i * 16 + row];
+      if (ro < 0) continue;
+      const f4_t x = *reinterpret_cast<const f4_t*>(&st[row * LD + col]);
+      const int64_t co = cols[wn + col];
+      if (vec && co >= 0) {
+        TC* dst = C + ro + co;
+        TC out[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          double y = alpha * (double)x[e];
+          if (beta != 0.0) y += beta * load_c(p, dst + e);
+          out[e] = store_c<TC>(p, y);
+        }
+        if constexpr (sizeof(TC) == 4) {
+          *reinterpret_cast<f4_t*>(dst) = f4_t{out[0], out[1], out[2], out[3]};
+        } else {
+          typedef double d2_t __attribute__((ext_vector_type(2)));
+          *reinterpret_cast<d2_t*>(dst) = d2_t{out[0], out[1]};
+          *reinterpret_cast<d2_t*>(dst + 2) = d2_t{out[2], out[3]};
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t ce = cols[wn + col + e];
+          if (ce < 0) continue;
+          TC* dst = C + ro + ce;
+          double y = alpha * (double)x[e];
+          if (beta != 0.0) y += beta * load_c(p, dst);
+          *dst = store_c<TC>(p, y);
+        }
+      }
+    }
+  }
+}
+
+template <typename TC, int BN>
+__global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
+  using G = Geo<BN>;
+  __shared__ __attribute__((aligned(1024))) char smem[lds_bytes<BN>()];
+
+  int tm, tn, split;
+  if (!tile_of_block(p, tm, tn, split)) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 2) * 128;
+  const int wn = (wave & 3) * G::kWN;
+  const uint32_t m0 = (uint32_t)tm * kBM;
+  const uint32_t n0 = (uint32_t)tn * BN;
+  const uint32_t kbeg = (uint32_t)split * (uint32_t)p.kchunk;
+  const uint32_t kend = min((uint32_t)p.K, kbeg + (uint32_t)p.kchunk);
+  const int nk = (int)((kend - kbeg) / kBK);  // k-aligned: whole tiles only
+  const char* __restrict__ A = static_cast<const char*>(p.a);
+  const char* __restrict__ B = static_cast<const char*>(p.b);
+
+  // DMA sources: chunk c (8 rows) of a tile is loaded by wave c % 8 as its
+  // instruction c / 8; lane l fills physical slot l % 8 of row 8c + l / 8,
+  // i.e. logical slot (l % 8) ^ swz(row) = k 4*slot .. 4*slot+3.
+  int64_t asrc[G::kAIns], bsrc[G::kBIns];
+  {
+    const int rl = lane >> 3, ph = lane & 7;
+#pragma unroll
+    for (int q = 0; q < G::kAIns; ++q) {
+      const int r = (q * 8 + wave) * 8 + rl;
+      const uint32_t rr = m0 + r;
+      const int64_t ro = rr < (uint32_t)p.M ? goff<false>(p.gm, rr) : 0;
+      asrc[q] = 4 * (ro + 4 * (ph ^ swz(r)));
+    }
+#pragma unroll
+    for (int q = 0; q < G::kBIns; ++q) {
+      const int r = (q * 8 + wave) * 8 + rl;
+      const uint32_t rr = n0 + r;
+      const int64_t ro = rr < (uint32_t)p.N ? goff<false>(p.gn, rr) : 0;
+      bsrc[q] = 4 * (ro + 4 * (ph ^ swz(r)));
+    }
+  }
+  KWalk<kBK> kw;
+  kw.init(p.gk, kbeg);
+  auto issue = [&](int stage, int kt) {
+    if (kt > 0) kw.next(p.gk);
+    char* sa = smem + stage * G::kStage;
+    char* sb = sa + G::kATile;
+    const int64_t ka = 4 * kw.oa, kb = 4 * kw.ob;
+#pragma unroll
+    for (int q = 0; q < G::kAIns; ++q)
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(A + asrc[q] + ka),
+                                       sa + (q * 8 + wave) * 1024, 16, 0, 0);
+#pragma unroll
+    for (int q = 0; q < G::kBIns; ++q)
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(B + bsrc[q] + kb),
+                                       sb + (q * 8 + wave) * 1024, 16, 0, 0);
+  };
+
+  f4_t acc[8][G::kWNB];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < G::kWNB; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+  // fragment offsets: rows wm + 16 i + lr (wn + 16 j + lr), slots 2 kq and 2 kq + 1
+  const int lr = lane & 15, kq = lane >> 4, sw = swz(lr);
+  const int x0 = ((2 * kq) ^ sw) << 4, x1 = ((2 * kq + 1) ^ sw) << 4;
+  const int abase = (wm + lr) * kRowBytes, bbase = (wn + lr) * kRowBytes;
+
+  auto split8 = [](const u4_t& w0, const u4_t& w1, bf8_t& hi, bf8_t& lo) {
+    const u4_t h = {hi_pair(w0.x, w0.y), hi_pair(w0.z, w0.w), hi_pair(w1.x, w1.y), hi_pair(w1.z, w1.w)};
+    const u4_t l = {lo_pair(w0.x, w0.y), lo_pair(w0.z, w0.w), lo_pair(w1.x, w1.y), lo_pair(w1.z, w1.w)};
+    hi = __builtin_bit_cast(bf8_t, h);
+    lo = __builtin_bit_cast(bf8_t, l);
+  };
+
+  issue(0, 0);
+  if (nk > 1) issue(1, 1);
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk)
+      wait_vmcnt<G::kIns>();  // this tile landed; the next one may still fly
+    else
+      wait_vmcnt<0>();
+    barrier_nofence();
+    const char* sa = smem + (kt & 1) * G::kStage;
+    const char* sb = sa + G::kATile;
+    bf8_t bh[G::kWNB], bl[G::kWNB];
+#pragma unroll
+    for (int j = 0; j < G::kWNB; ++j) {
+      const u4_t w0 = *reinterpret_cast<const u4_t*>(sb + bbase + j * 16 * kRowBytes + x0);
+      const u4_t w1 = *reinterpret_cast<const u4_t*>(sb + bbase + j * 16 * kRowBytes + x1);
+      split8(w0, w1, bh[j], bl[j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const u4_t w0 = *reinterpret_cast<const u4_t*>(sa + abase + i * 16 * kRowBytes + x0);
+      const u4_t w1 = *reinterpret_cast<const u4_t*>(sa + abase + i * 16 * kRowBytes + x1);
+      bf8_t ah, al;
+      split8(w0, w1, ah, al);
+#pragma unroll
+      for (int j = 0; j < G::kWNB; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < G::kWNB; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < G::kWNB; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+    }
+    barrier_nofence();  // every wave is done with this stage
+    if (kt + 2 < nk) issue(kt & 1, kt + 2);
+  }
+
+  write_tile_x<TC, BN>(p, acc, m0, n0, split, smem, wm, wn);
+}
+
+}  // namespace b3x
+
+bool contract_b3x_fits(int64_t M, int64_t N, int& bn) {
+  // 256-row tiles; the column tile that wastes the least of N (ties: 256)
+  if (M < 256 || N < 192) return false;
+  const int64_t w256 = (N + 255) / 256 * 256 - N;
+  const int64_t w192 = (N + 191) / 192 * 192 - N;
+  bn = w192 < w256 ? 192 : 256;
+  return true;
+}
+
+hipError_t launch_contract_b3x(const TcArgs& a, int bn, bool c_f64, hipStream_t s) {
+  const int blocks = a.per_xcd * 8;
+  if (bn == 256) {
+    if (c_f64)
+      hipLaunchKernelGGL((b3x::tc_b3x_kernel<double, 256>), dim3(blocks), dim3(b3x::kThreadsX), 0, s, a);
+    else
+      hipLaunchKernelGGL((b3x::tc_b3x_kernel<float, 256>), dim3(blocks), dim3(b3x::kThreadsX), 0, s, a);
+  } else if (bn == 192) {
+    if (c_f64)
+      hipLaunchKernelGGL((b3x::tc_b3x_kernel<double, 192>), dim3(blocks), dim3(b3x::kThreadsX), 0, s, a);
+    else
+      hipLaunchKernelGGL((b3x::tc_b3x_kernel<float, 192>), dim3(blocks), dim3(b3x::kThreadsX), 0, s, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mera

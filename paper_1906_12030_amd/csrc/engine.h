@@ -48,8 +48,8 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
 double contract_flops(const LabelDims& dims, const char* la, const char* lb, const char* lc);
 
 // ---- auxiliary kernels (aux.hip) ----
-// y[i] = (float) x[i]
-hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t s);
+// y[i] = (float) x[i]; with split, y holds split words (hi|lo bf16) of (float) x[i]
+hipError_t launch_to_f32(const double* x, float* y, int64_t n, bool split, hipStream_t s);
 // y[i] = a * x[i]
 hipError_t launch_scale(const double* x, double* y, double a, int64_t n, hipStream_t s);
 // fill y with value

@@ -124,7 +124,7 @@ int64_t ipow(int64_t b, int e) {
   return r;
 }
 
-// Layer tensors in the working type (converted copies for F32 / B3).
+// Layer tensors in the working type (converted copies for F32; split words for B3).
 struct LayerT {
   const void* u;
   const void* w;
@@ -136,8 +136,9 @@ LayerT working_layer(Ctx& cx, const mera_layer* L) {
   float* uf = static_cast<float*>(cx.take(ipow(din, 4), 4));
   float* wf = static_cast<float*>(cx.take(din * din * dout, 4));
   if (!cx.dry) {
-    cx.check(mera::launch_to_f32(L->u_d, uf, ipow(din, 4), cx.s), "to_f32(u)");
-    cx.check(mera::launch_to_f32(L->w_d, wf, din * din * dout, cx.s), "to_f32(w)");
+    const bool sp = cx.ar == Arith::B3;
+    cx.check(mera::launch_to_f32(L->u_d, uf, ipow(din, 4), sp, cx.s), "to_f32(u)");
+    cx.check(mera::launch_to_f32(L->w_d, wf, din * din * dout, sp, cx.s), "to_f32(w)");
   }
   return {uf, wf};
 }
@@ -146,7 +147,7 @@ LayerT working_layer(Ctx& cx, const mera_layer* L) {
 const void* working_op(Ctx& cx, const double* x, int64_t n) {
   if (cx.ar == Arith::F64) return x;
   float* xf = static_cast<float*>(cx.take(n, 4));
-  if (!cx.dry) cx.check(mera::launch_to_f32(x, xf, n, cx.s), "to_f32(op)");
+  if (!cx.dry) cx.check(mera::launch_to_f32(x, xf, n, cx.ar == Arith::B3, cx.s), "to_f32(op)");
   return xf;
 }
 

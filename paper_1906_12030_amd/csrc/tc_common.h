@@ -32,7 +32,21 @@ struct TcArgs {
   int32_t tiles_m, tiles_n, per_xcd, group_m;
   int32_t splits, kchunk;  // k range of split s: [s*kchunk, min(K, (s+1)*kchunk))
   int32_t cvec;            // 64-wide output column spans are contiguous (vector stores)
+  int32_t csplit;          // FP32 C is stored as split words (see pack_split)
 };
+
+// Split word: a 4-byte element holding x as two bf16 halves, hi = bf16_rne(x)
+// in bits 31..16 and lo = bf16_rne(x - hi) in bits 15..0.  The split-bf16
+// kernel reads its operands in this form, so the split of each value is done
+// once by the kernel that produces it instead of once per tile load.
+__device__ __forceinline__ uint32_t pack_split(float x) {
+  const __bf16 hi = (__bf16)x;
+  const __bf16 lo = (__bf16)(x - (float)hi);
+  return ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16) | __builtin_bit_cast(uint16_t, lo);
+}
+__device__ __forceinline__ float unpack_split(uint32_t w) {
+  return __uint_as_float(w & 0xffff0000u) + __uint_as_float(w << 16);
+}
 
 // Offset of linear group index idx in operand x (Second = false) or y.
 template <bool Second>
@@ -77,6 +91,10 @@ __device__ __forceinline__ bool tile_of_block(const TcArgs& p, int& tm, int& tn,
 
 hipError_t launch_contract_b3(const TcArgs& a, bool akc, bool va, bool bnc, bool vb, bool kal,
                               bool c_f64, hipStream_t s);
+// Large-tile split-bf16 kernel (both operands contiguous along k, k-aligned):
+// whether an M x N output suits it (and its column tile), and the launch.
+bool contract_b3x_fits(int64_t M, int64_t N, int& bn);
+hipError_t launch_contract_b3x(const TcArgs& a, int bn, bool c_f64, hipStream_t s);
 
 }  // namespace mera
 
@@ -139,15 +157,23 @@ struct TileLoad {
 
   // k-aligned tile whose k offset (uniform) is kb: no masking at all
   __device__ __forceinline__ void load_at(const T* __restrict__ base, int64_t kb) {
+    load_at(base, kb, r);
+  }
+  __device__ __forceinline__ void load_at(const T* __restrict__ base, int64_t kb, T (&d)[NP][V]) {
 #pragma unroll
-    for (int i = 0; i < NP; ++i) load_vec<T, V>(base + roff[KC ? i : 0] + kb + kd[KC ? 0 : i], r[i]);
+    for (int i = 0; i < NP; ++i) load_vec<T, V>(base + roff[KC ? i : 0] + kb + kd[KC ? 0 : i], d[i]);
   }
 
   __device__ __forceinline__ void load(const T* __restrict__ base, const Group& gk, uint32_t k0,
                                        uint32_t K) {
+    load(base, gk, k0, K, r);
+  }
+  // into a caller-held register tile d (several tiles in flight)
+  __device__ __forceinline__ void load(const T* __restrict__ base, const Group& gk, uint32_t k0,
+                                       uint32_t K, T (&d)[NP][V]) {
     if constexpr (KAL) {
       const int64_t kb = goff<KSecond>(gk, k0);
-      load_at(base, kb);
+      load_at(base, kb, d);
     } else {
       if constexpr (KC) {
         const uint32_t k = k0 + vec;
@@ -156,10 +182,10 @@ struct TileLoad {
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
           if (kok && rok[i]) {
-            load_vec<T, V>(base + roff[i] + ko, r[i]);
+            load_vec<T, V>(base + roff[i] + ko, d[i]);
           } else {
 #pragma unroll
-            for (int v = 0; v < V; ++v) r[i][v] = T(0);
+            for (int v = 0; v < V; ++v) d[i][v] = T(0);
           }
         }
       } else {
@@ -167,10 +193,10 @@ struct TileLoad {
         for (int i = 0; i < NP; ++i) {
           const uint32_t k = k0 + line + i * LPP;
           if (k < K && rok[0]) {
-            load_vec<T, V>(base + roff[0] + goff<KSecond>(gk, k), r[i]);
+            load_vec<T, V>(base + roff[0] + goff<KSecond>(gk, k), d[i]);
           } else {
 #pragma unroll
-            for (int v = 0; v < V; ++v) r[i][v] = T(0);
+            for (int v = 0; v < V; ++v) d[i][v] = T(0);
           }
         }
       }
@@ -180,7 +206,9 @@ struct TileLoad {
 
 // Uniform walk over k-tiles of a k group whose innermost leg's extent is a
 // multiple of the tile: keeps the leg digits of the tile start and its offsets
-// in both operands, advancing by carries instead of divisions.
+// in both operands, advancing by carries instead of divisions.  Digits are
+// held innermost first (dig[0] = innermost leg), so a step is one add and one
+// compare unless the innermost leg wraps.
 template <int BK>
 struct KWalk {
   int32_t dig[kMaxDims];
@@ -189,38 +217,33 @@ struct KWalk {
     oa = 0;
     ob = 0;
 #pragma unroll
-    for (int d = kMaxDims - 1; d >= 0; --d) {
-      dig[d] = 0;
-      if (d < g.nd) {
+    for (int j = 0; j < kMaxDims; ++j) {
+      dig[j] = 0;
+      if (j < g.nd) {
+        const int d = g.nd - 1 - j;
         const uint32_t sz = (uint32_t)g.size[d];
         const uint32_t q = k0 / sz;
-        dig[d] = (int32_t)(k0 - q * sz);
-        oa += (int64_t)dig[d] * g.sx[d];
-        ob += (int64_t)dig[d] * g.sy[d];
+        dig[j] = (int32_t)(k0 - q * sz);
+        oa += (int64_t)dig[j] * g.sx[d];
+        ob += (int64_t)dig[j] * g.sy[d];
         k0 = q;
       }
     }
   }
   __device__ __forceinline__ void next(const Group& g) {
     const int in = g.nd - 1;
-    // innermost leg (index known only at run time; unrolled over the legal range)
+    dig[0] += BK;
+    oa += (int64_t)BK * g.sx[in];
+    ob += (int64_t)BK * g.sy[in];
+    // carries toward the outer legs (rare: once per size[in] / BK steps)
 #pragma unroll
-    for (int d = kMaxDims - 1; d >= 0; --d) {
-      if (d == in) {
-        dig[d] += BK;
-        oa += (int64_t)BK * g.sx[d];
-        ob += (int64_t)BK * g.sy[d];
-      }
-    }
-    // carries toward the outer legs
-#pragma unroll
-    for (int d = kMaxDims - 1; d >= 1; --d) {
-      if (d <= in && dig[d] >= g.size[d]) {
-        dig[d] -= g.size[d];
-        oa += g.sx[d - 1] - (int64_t)g.size[d] * g.sx[d];
-        ob += g.sy[d - 1] - (int64_t)g.size[d] * g.sy[d];
-        dig[d - 1] += 1;
-      }
+    for (int j = 0; j < kMaxDims - 1; ++j) {
+      const int d = in - j;
+      if (j >= in || dig[j] < g.size[d]) break;
+      dig[j] -= g.size[d];
+      dig[j + 1] += 1;
+      oa += g.sx[d - 1] - (int64_t)g.size[d] * g.sx[d];
+      ob += g.sy[d - 1] - (int64_t)g.size[d] * g.sy[d];
     }
   }
 };
@@ -245,6 +268,23 @@ __device__ __forceinline__ void stage_c_offsets(const TcArgs& p, uint32_t m0, ui
       cols[i - TM] = o;
     }
   }
+}
+
+// Element of C as a number / a number as C's element (split words when
+// p.csplit; the bits travel in a float).
+template <typename TC>
+__device__ __forceinline__ double load_c(const TcArgs& p, const TC* src) {
+  if constexpr (sizeof(TC) == 4) {
+    if (p.csplit) return (double)unpack_split(__float_as_uint(*src));
+  }
+  return (double)*src;
+}
+template <typename TC>
+__device__ __forceinline__ TC store_c(const TcArgs& p, double y) {
+  if constexpr (sizeof(TC) == 4) {
+    if (p.csplit) return __uint_as_float(pack_split((float)y));
+  }
+  return (TC)y;
 }
 
 // Epilogue shared by the MFMA kernels.  Each wave owns a 64x64 block of the
@@ -273,6 +313,8 @@ __device__ __forceinline__ void write_tile(const TcArgs& p, ACC (&acc)[4][4], ui
   const double alpha = p.splits > 1 ? 1.0 : p.alpha;
   const double beta = p.splits > 1 ? 0.0 : p.beta;
   const bool vec = p.cvec != 0;
+  // unrolled: acc must stay in registers (a runtime index would demote it to scratch)
+#pragma unroll
   for (int i = 0; i < 4; ++i) {
     __syncthreads();  // offsets staged / previous row group consumed
 #pragma unroll
@@ -301,8 +343,8 @@ __device__ __forceinline__ void write_tile(const TcArgs& p, ACC (&acc)[4][4], ui
 #pragma unroll
         for (int e = 0; e < VA; ++e) {
           double y = alpha * (double)v[e];
-          if (beta != 0.0) y += beta * (double)dst[e];
-          out[e] = (TC)y;
+          if (beta != 0.0) y += beta * load_c(p, dst + e);
+          out[e] = store_c<TC>(p, y);
         }
         if constexpr (sizeof(TC) * VA == 16) {
           typedef TC ot __attribute__((ext_vector_type(VA)));
@@ -327,8 +369,8 @@ __device__ __forceinline__ void write_tile(const TcArgs& p, ACC (&acc)[4][4], ui
           if (ce < 0) continue;
           TC* dst = C + ro + ce;
           double y = alpha * (double)v[e];
-          if (beta != 0.0) y += beta * (double)(*dst);
-          *dst = (TC)y;
+          if (beta != 0.0) y += beta * load_c(p, dst);
+          *dst = store_c<TC>(p, y);
         }
       }
     }
