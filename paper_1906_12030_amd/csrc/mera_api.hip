@@ -163,15 +163,22 @@ void set_dims(Ctx& cx, int din, int dout) {
 
 // Shared small tensors of one layer.
 // N and M appear in several layouts so that every chi^9 contraction sums over
-// legs that are contiguous (in the same order) in both of its operands.
+// legs that are contiguous (in the same order) in both of its operands.  The
+// split-bf16 path keeps N3 and M3 with those legs innermost ("k-contiguous"),
+// which lets its large-tile kernel load both operands straight into LDS.
 struct Pieces {
   void *Lp, *Rp;
   void* N;   // [r s b d j]
-  void* N3;  // [r b s d j]
+  void* N3;  // [r b s d j]; split bf16: [s d j r b]
   void* M;   // [p q c a j]
   void* M1;  // [q p c j a]
-  void* M3;  // [p c q a j]
+  void* M3;  // [p c q a j]; split bf16: [p a j c q]
+  const char* n3;  // labels of N3 as (R B s D J) legs
+  const char* m3;  // labels of M3 as (p C Q A J) legs
 };
+
+// Layouts for the split-bf16 path (see Pieces and x_copies).
+bool k_contiguous_layouts(const Ctx& cx) { return cx.ar == Arith::B3; }
 
 Pieces build_pieces(Ctx& cx, const LayerT& t, int64_t din, int64_t dout) {
   Pieces pc;
@@ -185,17 +192,42 @@ Pieces build_pieces(Ctx& cx, const LayerT& t, int64_t din, int64_t dout) {
   cx.c(t.w, "xai", t.w, "xAI", pc.Lp, "aiAI", false, 1.0, 0.0);
   cx.c(t.w, "dyk", t.w, "DyK", pc.Rp, "dkDK", false, 1.0, 0.0);
   cx.c(t.w, "bcj", t.u, "rscd", pc.N, "rsbdj", false, 1.0, 0.0);
-  cx.c(t.w, "bcj", t.u, "rscd", pc.N3, "rbsdj", false, 1.0, 0.0);
+  const bool kc = k_contiguous_layouts(cx);
+  cx.c(t.w, "bcj", t.u, "rscd", pc.N3, kc ? "sdjrb" : "rbsdj", false, 1.0, 0.0);
+  pc.n3 = kc ? "sDJRB" : "RBsDJ";
+  pc.m3 = kc ? "pAJCQ" : "pCQAJ";
   cx.c(t.u, "pqab", t.w, "bcj", pc.M, "pqcaj", false, 1.0, 0.0);
   cx.c(t.u, "pqab", t.w, "bcj", pc.M1, "qpcja", false, 1.0, 0.0);
-  cx.c(t.u, "pqab", t.w, "bcj", pc.M3, "pcqaj", false, 1.0, 0.0);
+  cx.c(t.u, "pqab", t.w, "bcj", pc.M3, kc ? "pajcq" : "pcqaj", false, 1.0, 0.0);
   return pc;
 }
 
 // X[j a d A D J] = sum Lp[a i A I] rho[i j k I J K] Rp[d k D K]; keeps X1 = Lp.rho.
+// X may be null when only the k-contiguous copies are needed.
 void build_x(Ctx& cx, const Pieces& pc, const void* rho, void* X1, void* X) {
   cx.c(pc.Lp, "aiAI", rho, "ijkIJK", X1, "ajkAJK", false, 1.0, 0.0);
-  cx.c(X1, "ajkAJK", pc.Rp, "dkDK", X, "djaADJ", false, 1.0, 0.0);
+  if (X) cx.c(X1, "ajkAJK", pc.Rp, "dkDK", X, "djaADJ", false, 1.0, 0.0);
+}
+
+// Copies of X for the first chi^9 contraction of each chain, with the summed
+// legs innermost: [a A D J d j] (left chain, sums d j) and [d D A J j a]
+// (right chain, sums j a).  Without them X's summed legs come first and the
+// contraction's second operand is contiguous along its output legs.
+struct XCopies {
+  const void* l;  // labels xl
+  const void* r;  // labels xr
+  const char* xl;
+  const char* xr;
+};
+
+XCopies x_copies(Ctx& cx, const Pieces& pc, const void* X1, const void* X, int64_t din,
+                 int64_t dout) {
+  if (!k_contiguous_layouts(cx)) return {X, X, "djaADJ", "djaADJ"};
+  void* xl = cx.take_t(ipow(din, 4) * dout * dout);
+  void* xr = cx.take_t(ipow(din, 4) * dout * dout);
+  cx.c(X1, "ajkAJK", pc.Rp, "dkDK", xl, "aADJdj", false, 1.0, 0.0);
+  cx.c(X1, "ajkAJK", pc.Rp, "dkDK", xr, "dDAJja", false, 1.0, 0.0);
+  return {xl, xr, "aADJdj", "dDAJja"};
 }
 
 struct Bufs {
@@ -227,10 +259,11 @@ int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_
   const void* rho = working_op(cx, rho_in, ipow(dout, 6));
   Pieces pc = build_pieces(cx, t, din, dout);
   void* X1 = cx.take_t(din * din * ipow(dout, 4));
-  void* X = cx.take_t(ipow(din, 4) * dout * dout);
+  void* X = k_contiguous_layouts(cx) ? nullptr : cx.take_t(ipow(din, 4) * dout * dout);
   const int64_t R = (din + slices - 1) / slices;
-  Bufs b = take_bufs(cx, din, dout, R);
   build_x(cx, pc, rho, X1, X);
+  const XCopies xc = x_copies(cx, pc, X1, X, din, dout);
+  Bufs b = take_bufs(cx, din, dout, R);
   const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
   const LabelDims full = cx.dims;
   const size_t es = cx.elem();
@@ -240,7 +273,7 @@ int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_
       cx.dims = full;
       cx.dims.d['r'] = std::min(R, din - r0);
       const char* n_s = static_cast<const char*>(pc.N) + r0 * ipow(din, 3) * dout * es;  // N[r0, ...]
-      cx.c(n_s, "rsbdj", X, "djaADJ", b.big, "rsbaADJ", false, 1.0, 0.0);
+      cx.c(n_s, "rsbdj", xc.l, xc.xl, b.big, "rsbaADJ", false, 1.0, 0.0);
       cx.c(b.big, "rsbaADJ", pc.N, "RsBDJ", b.mid, "rabABR", false, 1.0, 0.0);
       cx.c(b.mid, "rabABR", t.u, "pqab", b.mid2, "pqrABR", false, 1.0, 0.0);
       cx.c(b.mid2, "pqrABR", t.u, "PQAB", rho_out + r0 * ipow(din, 3), "pqrPQR", true, wgt, 0.0, &full);
@@ -253,7 +286,7 @@ int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_
       cx.dims = full;
       cx.dims.d['q'] = std::min(R, din - q0);
       const char* m_s = static_cast<const char*>(pc.M1) + q0 * ipow(din, 3) * dout * es;  // M1[q0, ...]
-      cx.c(m_s, "qpcja", X, "djaADJ", b.big, "pqcdDAJ", false, 1.0, 0.0);
+      cx.c(m_s, "qpcja", xc.r, xc.xr, b.big, "pqcdDAJ", false, 1.0, 0.0);
       cx.c(b.big, "pqcdDAJ", pc.M, "pQCAJ", b.mid, "qcdDCQ", false, 1.0, 0.0);
       cx.c(b.mid, "qcdDCQ", t.u, "rscd", b.mid2, "qrsCDQ", false, 1.0, 0.0);
       cx.c(b.mid2, "qrsCDQ", t.u, "RSCD", rho_out + q0 * ipow(din, 5), "qrsQRS", true, wgt,
@@ -297,14 +330,14 @@ int run_ascend(Ctx& cx, const mera_layer* L, const double* h_in, double* h_out, 
   if (placement != MERA_RIGHT) {
     cx.c(o, "pqrPQR", t.u, "PQAB", b.mid2, "pqrABR", false, wgt, 0.0);
     cx.c(b.mid2, "pqrABR", t.u, "pqab", b.mid, "rabARB", false, 1.0, 0.0);
-    cx.c(b.mid, "rabARB", pc.N3, "RBsDJ", b.big, "rsbaADJ", false, 1.0, 0.0);
+    cx.c(b.mid, "rabARB", pc.N3, pc.n3, b.big, "rsbaADJ", false, 1.0, 0.0);
     cx.c(pc.N, "rsbdj", b.big, "rsbaADJ", Xb, "djaADJ", false, 1.0, 0.0);
     first = false;
   }
   if (placement != MERA_LEFT) {
     cx.c(o, "qrsQRS", t.u, "RSCD", b.mid2, "qrsCDQ", false, wgt, 0.0);
     cx.c(b.mid2, "qrsCDQ", t.u, "rscd", b.mid, "qcdDCQ", false, 1.0, 0.0);
-    cx.c(b.mid, "qcdDCQ", pc.M3, "pCQAJ", b.big, "pqcdADJ", false, 1.0, 0.0);
+    cx.c(b.mid, "qcdDCQ", pc.M3, pc.m3, b.big, "pqcdADJ", false, 1.0, 0.0);
     cx.c(pc.M, "pqcaj", b.big, "pqcdADJ", Xb, "djaADJ", false, 1.0, first ? 0.0 : 1.0);
   }
   cx.c(Xb, "djaADJ", pc.Rp, "dkDK", Z1, "ajkAJK", false, 1.0, 0.0);
@@ -336,6 +369,7 @@ int run_env(Ctx& cx, const mera_layer* L, const double* h_in, const double* rho_
   void* dRp = want_u ? nullptr : cx.take_t(din * din * dout * dout);
   // env accumulators: written in FP64 directly by the final contractions
   build_x(cx, pc, rho, X1, X);
+  const XCopies xc = want_u ? x_copies(cx, pc, X1, X, din, dout) : XCopies{X, X, "djaADJ", "djaADJ"};
   const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
   bool first_env = true;
   bool first_dx = true;
@@ -348,12 +382,12 @@ int run_env(Ctx& cx, const mera_layer* L, const double* h_in, const double* rho_
     cx.c(h, "PQRpqr", t.u, "PQAB", b.mid2, "pqrABR", false, wgt, 0.0);  // G1
     if (want_u) {
       // forward Z = (N . X) . N' for the derivative of the closing ket uL
-      cx.c(pc.N, "rsbdj", X, "djaADJ", b.big, "rsbaADJ", false, 1.0, 0.0);
+      cx.c(pc.N, "rsbdj", xc.l, xc.xl, b.big, "rsbaADJ", false, 1.0, 0.0);
       cx.c(b.big, "rsbaADJ", pc.N, "RsBDJ", b.mid, "rabABR", false, 1.0, 0.0);
       acc_env(b.mid2, "pqrABR", b.mid, "rabABR", "pqab");
     }
     cx.c(b.mid2, "pqrABR", t.u, "pqab", b.mid, "rabARB", false, 1.0, 0.0);   // G2
-    cx.c(b.mid, "rabARB", pc.N3, "RBsDJ", b.big, "rsbaADJ", false, 1.0, 0.0);  // G3
+    cx.c(b.mid, "rabARB", pc.N3, pc.n3, b.big, "rsbaADJ", false, 1.0, 0.0);  // G3
     cx.c(b.big, "rsbaADJ", X, "djaADJ", dN, "rsbdj", false, 1.0, 0.0);        // dN
     if (want_u) {
       acc_env(dN, "rsbdj", t.w, "bcj", "rscd");  // uR inside N
@@ -366,12 +400,12 @@ int run_env(Ctx& cx, const mera_layer* L, const double* h_in, const double* rho_
   if (placement != MERA_LEFT) {
     cx.c(h, "QRSqrs", t.u, "RSCD", b.mid2, "qrsCDQ", false, wgt, 0.0);  // H1
     if (want_u) {
-      cx.c(pc.M1, "qpcja", X, "djaADJ", b.big, "pqcdDAJ", false, 1.0, 0.0);
+      cx.c(pc.M1, "qpcja", xc.r, xc.xr, b.big, "pqcdDAJ", false, 1.0, 0.0);
       cx.c(b.big, "pqcdDAJ", pc.M, "pQCAJ", b.mid, "qcdDCQ", false, 1.0, 0.0);
       acc_env(b.mid2, "qrsCDQ", b.mid, "qcdDCQ", "rscd");
     }
     cx.c(b.mid2, "qrsCDQ", t.u, "rscd", b.mid, "qcdDCQ", false, 1.0, 0.0);   // H2
-    cx.c(b.mid, "qcdDCQ", pc.M3, "pCQAJ", b.big, "pqcdADJ", false, 1.0, 0.0);  // H3
+    cx.c(b.mid, "qcdDCQ", pc.M3, pc.m3, b.big, "pqcdADJ", false, 1.0, 0.0);  // H3
     cx.c(b.big, "pqcdADJ", X, "djaADJ", dM, "pqcaj", false, 1.0, 0.0);        // dM
     if (want_u) {
       acc_env(dM, "pqcaj", t.w, "bcj", "pqab");  // uL inside M
