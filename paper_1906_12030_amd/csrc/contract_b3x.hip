@@ -9,9 +9,9 @@
 //     twice the tile edge of the 128 x 128 kernel halves the bytes that
 //     have to come through L2 per flop;
 //   * operand k-tiles (32 split words per row) go straight from global
-//     memory into LDS with global_load_lds_dwordx4, in a two-stage ring:
-//     the loads of tile kt+1 fly while the MFMAs of tile kt run, and no
-//     registers are spent on staging;
+//     memory into LDS with global_load_lds_dwordx4, in a two-stage ring
+//     with one barrier per k-tile: the loads of tile kt+1 fly while the
+//     MFMAs of tile kt run, and no registers are spent on staging;
 //   * LDS rows are 128 bytes (eight 16-byte slots of 4 k each); slot s of
 //     row r is stored at s ^ swz(r) so that the fragment reads of a
 //     half-wave (16 rows x 2 slots) hit 32 distinct 16-byte slots modulo
@@ -75,7 +75,6 @@ struct Geo {
   static constexpr int kStage = kATile + kBTile;
   static constexpr int kAIns = kBM / 64;  // 1 KB (8-row) DMA chunks per wave for A
   static constexpr int kBIns = BN / 64;   // and for B
-  static constexpr int kIns = kAIns + kBIns;
   static_assert(BN % 64 == 0 && BN <= 256, "tile width");
 };
 
@@ -243,14 +242,15 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
     lo = __builtin_bit_cast(bf8_t, l);
   };
 
+  // One barrier per k-tile: after a wave's own loads of tile kt have landed
+  // it waits at the barrier, which then also proves that every wave has
+  // finished tile kt-1, so the loads of tile kt+1 may overwrite that stage
+  // while the MFMAs of tile kt run.
   issue(0, 0);
-  if (nk > 1) issue(1, 1);
   for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk)
-      wait_vmcnt<G::kIns>();  // this tile landed; the next one may still fly
-    else
-      wait_vmcnt<0>();
+    wait_vmcnt<0>();
     barrier_nofence();
+    if (kt + 1 < nk) issue((kt + 1) & 1, kt + 1);
     const char* sa = smem + (kt & 1) * G::kStage;
     const char* sb = sa + G::kATile;
     bf8_t bh[G::kWNB], bl[G::kWNB];
@@ -260,12 +260,20 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
       const u4_t w1 = *reinterpret_cast<const u4_t*>(sb + bbase + j * 16 * kRowBytes + x1);
       split8(w0, w1, bh[j], bl[j]);
     }
+    // A fragments through a ring of three: the reads of block i+2 are in
+    // flight while block i's MFMAs run
+    u4_t ra[3][2];
+    auto read_a = [&](int i, u4_t (&r)[2]) {
+      r[0] = *reinterpret_cast<const u4_t*>(sa + abase + i * 16 * kRowBytes + x0);
+      r[1] = *reinterpret_cast<const u4_t*>(sa + abase + i * 16 * kRowBytes + x1);
+    };
+    read_a(0, ra[0]);
+    read_a(1, ra[1]);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const u4_t w0 = *reinterpret_cast<const u4_t*>(sa + abase + i * 16 * kRowBytes + x0);
-      const u4_t w1 = *reinterpret_cast<const u4_t*>(sa + abase + i * 16 * kRowBytes + x1);
+      if (i + 2 < 8) read_a(i + 2, ra[(i + 2) % 3]);
       bf8_t ah, al;
-      split8(w0, w1, ah, al);
+      split8(ra[i % 3][0], ra[i % 3][1], ah, al);
 #pragma unroll
       for (int j = 0; j < G::kWNB; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
@@ -276,9 +284,8 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
       for (int j = 0; j < G::kWNB; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
     }
-    barrier_nofence();  // every wave is done with this stage
-    if (kt + 2 < nk) issue(kt & 1, kt + 2);
   }
+  barrier_nofence();  // the epilogue reuses the stages
 
   write_tile_x<TC, BN>(p, acc, m0, n0, split, smem, wm, wn);
 }
