@@ -181,6 +181,17 @@ int mera_profile_end(mera_profile_entry* out, int32_t max_entries, int32_t* n_ou
  * for the other ops.  Pure host function. */
 size_t mera_workspace_bytes_min(int op, int32_t din, int32_t dout, int precision, int placement);
 
+/* Measured matrix-core throughput of this device in TFLOP/s, the peak the
+ * contraction kernels are compared against: kind 0 = v_mfma_f32_16x16x32_bf16,
+ * 1 = v_mfma_f32_16x16x4_f32, 2 = v_mfma_f64_16x16x4_f64, each with eight
+ * independent accumulator chains per wave and register operands only, 8
+ * waves per SIMD on every CU; best of three timed launches after a warm-up.
+ * scratch_d: caller-owned device buffer of at least 2 MiB (written).
+ * Synchronous on the default stream.  Diagnostic, not part of the hot path.
+ * Errors: MERA_EINVAL (kind, null pointers), MERA_EWORKSPACE (scratch too
+ * small; checked before any HIP call), MERA_EDEVICE. */
+int mera_mfma_peak(int kind, void* scratch_d, size_t scratch_bytes, double* tflops_out);
+
 /* Static text for a status code. */
 const char* mera_strerror(int status);
 

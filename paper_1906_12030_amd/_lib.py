@@ -22,7 +22,7 @@ EXPORTED = (
     "mera_ascend", "mera_descend", "mera_env_u", "mera_env_w", "mera_polar_update",
     "mera_fixed_point_rho", "mera_energy", "mera_tfim_hamiltonian", "mera_workspace_bytes",
     "mera_strerror", "mera_last_error", "mera_flops", "mera_profile_begin", "mera_profile_end",
-    "mera_workspace_bytes_min",
+    "mera_workspace_bytes_min", "mera_mfma_peak",
 )
 
 
@@ -73,6 +73,8 @@ def load() -> ctypes.CDLL:
     lib.mera_strerror.restype = ctypes.c_char_p
     lib.mera_last_error.argtypes = []
     lib.mera_last_error.restype = ctypes.c_char_p
+    lib.mera_mfma_peak.argtypes = [ctypes.c_int, vp, sz, ctypes.POINTER(dbl)]
+    lib.mera_mfma_peak.restype = ctypes.c_int
     lib.mera_profile_begin.argtypes = []
     lib.mera_profile_begin.restype = ctypes.c_int
     lib.mera_profile_end.argtypes = [ctypes.POINTER(MeraProfileEntry), i32, ctypes.POINTER(i32)]
@@ -139,6 +141,13 @@ def mera_workspace_bytes_min(op, din, dout, precision, placement):
 
 def mera_flops(op, din, dout, placement):
     return float(load().mera_flops(op, din, dout, placement))
+
+
+def mera_mfma_peak(kind, scratch_ptr, scratch_bytes):
+    """(status, TFLOP/s) of the matrix-core microbenchmark (0 bf16, 1 f32, 2 f64)."""
+    t = ctypes.c_double(0.0)
+    st = load().mera_mfma_peak(kind, scratch_ptr, scratch_bytes, ctypes.byref(t))
+    return st, float(t.value)
 
 
 def mera_profile_begin():

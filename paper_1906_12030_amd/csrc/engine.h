@@ -47,6 +47,12 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
 // Flop count of the same contraction without launching anything.
 double contract_flops(const LabelDims& dims, const char* la, const char* lb, const char* lc);
 
+// ---- MFMA throughput microbenchmark (peak.hip) ----
+// kind 0: bf16 16x16x32, 1: f32 16x16x4, 2: f64 16x16x4; `out` holds
+// blocks*256 floats; flops of one launch = blocks*4 waves*iters*per_wave_iter.
+hipError_t run_mfma_peak(int kind, float* out, int blocks, int iters, hipStream_t s);
+double mfma_peak_flops_per_wave_iter(int kind);
+
 // ---- auxiliary kernels (aux.hip) ----
 // y[i] = (float) x[i]; with split, y holds split words (hi|lo bf16) of (float) x[i]
 hipError_t launch_to_f32(const double* x, float* y, int64_t n, bool split, hipStream_t s);

@@ -570,6 +570,47 @@ int mera_profile_end(mera_profile_entry* out, int32_t max_entries, int32_t* n_ou
   return rc;
 }
 
+int mera_mfma_peak(int kind, void* scratch_d, size_t scratch_bytes, double* tflops_out) {
+  // 2048 workgroups x 4 waves = 8 waves per SIMD on 256 CUs; about 5 ms per launch
+  constexpr int kBlocks = 2048;
+  if (!tflops_out || !scratch_d || kind < 0 || kind > 2) {
+    set_err("mfma peak: kind must be 0 (bf16), 1 (f32) or 2 (f64); buffers non-null");
+    return MERA_EINVAL;
+  }
+  if (scratch_bytes < sizeof(float) * kBlocks * 256) {
+    set_err("mfma peak: scratch needs 2 MiB");
+    return MERA_EWORKSPACE;
+  }
+  const int iters = kind == 0 ? 2048 : 8192;
+  float* out = static_cast<float*>(scratch_d);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = MERA_OK;
+  float best = 1e30f;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    set_err(hipGetErrorString(hipGetLastError()));
+    rc = MERA_EDEVICE;
+  }
+  for (int rep = 0; rc == MERA_OK && rep < 4; ++rep) {  // the first launch warms the clocks up
+    float ms = 0.f;
+    if (hipEventRecord(e0, nullptr) != hipSuccess ||
+        mera::run_mfma_peak(kind, out, kBlocks, iters, nullptr) != hipSuccess ||
+        hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      set_err(hipGetErrorString(hipGetLastError()));
+      rc = MERA_EDEVICE;
+    } else if (rep > 0 && ms < best) {
+      best = ms;
+    }
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (rc == MERA_OK) {
+    const double flops = (double)kBlocks * 4 * iters * mera::mfma_peak_flops_per_wave_iter(kind);
+    *tflops_out = flops / (best * 1e-3) / 1e12;
+  }
+  return rc;
+}
+
 int mera_descend(const mera_layer* layer, const double* rho_in_d, double* rho_out_d, int placement,
                  int precision, void* ws_d, size_t ws_bytes, void* hip_stream) {
   int st = check_layer(layer);

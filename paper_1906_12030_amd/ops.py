@@ -183,3 +183,13 @@ def flops(op: str, din: int, dout: int, placement="avg") -> float:
     ops = {"ascend": _lib.MERA_OP_ASCEND, "descend": _lib.MERA_OP_DESCEND, "env_u": _lib.MERA_OP_ENV_U,
            "env_w": _lib.MERA_OP_ENV_W, "fixed_point_iter": _lib.MERA_OP_FIXED_POINT}
     return _lib.mera_flops(ops[op], din, dout, _place(placement))
+
+
+def mfma_peak(kind: str = "bf16") -> float:
+    """Measured matrix-core throughput (TFLOP/s) of the current device for one
+    MFMA shape: "bf16" (16x16x32), "fp32" or "fp64" (16x16x4)."""
+    k = {"bf16": 0, "fp32": 1, "fp64": 2}[kind]
+    scratch = torch.empty(1 << 19, dtype=torch.float32, device="cuda")
+    st, tf = _lib.mera_mfma_peak(k, scratch.data_ptr(), scratch.numel() * 4)
+    _lib.check(st, "mera_mfma_peak")
+    return tf

@@ -129,3 +129,13 @@ def test_native_hamiltonian_matches_oracle(lib):
         c_ref = np.linalg.eigvalsh(h3)[-1]
         assert abs(c - c_ref) < 1e-14
         assert np.abs(np.array(h).reshape(8, 8) - (h3 - c_ref * np.eye(8))).max() < 1e-14
+
+
+def test_mfma_peak_argument_checks(lib):
+    fake = 4096
+    st, _ = _lib.mera_mfma_peak(3, fake, 1 << 21)
+    assert st == _lib.MERA_EINVAL
+    st, _ = _lib.mera_mfma_peak(0, None, 1 << 21)
+    assert st == _lib.MERA_EINVAL
+    st, _ = _lib.mera_mfma_peak(0, fake, 1 << 20)
+    assert st == _lib.MERA_EWORKSPACE

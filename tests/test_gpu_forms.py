@@ -137,3 +137,12 @@ def test_scaling_dimensions_gpu_vs_oracle(mods):
     assert np.abs(np.abs(lam_g) - np.abs(lam_o)).max() < 1e-8
     assert abs(dims_g[0]) < 1e-10
     assert abs(dims_g[1] - 0.125) < 0.02
+
+
+def test_mfma_peak_microbenchmark(mods):
+    """The measured matrix-core throughput is positive and below the published dense peaks."""
+    ops = mods[0]
+    for kind, published in (("bf16", 2516.6), ("fp32", 157.3), ("fp64", 78.6)):
+        tf = ops.mfma_peak(kind)
+        say(f"  mfma peak {kind}: {tf:.1f} TFLOP/s (published {published})")
+        assert 0.2 * published < tf < 1.05 * published
