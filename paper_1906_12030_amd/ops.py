@@ -57,8 +57,32 @@ class Workspace:
         aligned = (ptr + 255) & ~255
         return aligned, cur.numel() - (aligned - ptr)
 
+    def size(self, device) -> int:
+        cur = self.buf.get((torch.device(device).index,))
+        return 0 if cur is None else cur.numel()
+
     def release(self):
         self.buf.clear()
+
+    def for_op(self, op: int, din: int, dout: int, q: int, p: int, device) -> tuple[int, int]:
+        """Workspace for one call: the full size when it fits on the device, else as much as
+        fits (at least mera_workspace_bytes_min: the chi^7 intermediates are then sliced)."""
+        full = _lib.mera_workspace_bytes(op, din, dout, q, p)
+        cur = self.size(device)
+        if full <= cur:
+            return self.get(full, device)
+        free, _ = torch.cuda.mem_get_info(device)
+        cached = torch.cuda.memory_reserved(device) - torch.cuda.memory_allocated(device)
+        avail = free + cached + cur - (2 << 30)  # keep 2 GiB for the caller's tensors
+        if full <= avail:
+            return self.get(full, device)
+        # sliced: leave a quarter of the device to the caller's chi^6 tensors
+        budget = avail - torch.cuda.get_device_properties(device).total_memory // 4
+        least = _lib.mera_workspace_bytes_min(op, din, dout, q, p)
+        if least > max(budget, avail - (8 << 30)):
+            raise MemoryError(f"workspace: {least / 1e9:.1f} GB needed even with slicing, "
+                              f"{avail / 1e9:.1f} GB available")
+        return self.get(max(least, budget), device)
 
 
 WORKSPACE = Workspace()
@@ -82,8 +106,7 @@ def ascend(layer: Layer, h: torch.Tensor, placement="avg", precision="fp64", out
     p, q = _place(placement), _prec(precision)
     if out is None:
         out = torch.empty((layer.dout,) * 6, dtype=torch.float64, device=h.device)
-    nb = _lib.mera_workspace_bytes(_lib.MERA_OP_ASCEND, layer.din, layer.dout, q, p)
-    ws, wsb = WORKSPACE.get(nb, h.device)
+    ws, wsb = WORKSPACE.for_op(_lib.MERA_OP_ASCEND, layer.din, layer.dout, q, p, h.device)
     _lib.check(_lib.mera_ascend(layer.c(), h.data_ptr(), out.data_ptr(), p, q, ws, wsb, _stream(h.device)), "mera_ascend")
     return out
 
@@ -94,8 +117,7 @@ def descend(layer: Layer, rho: torch.Tensor, placement="avg", precision="fp64", 
     p, q = _place(placement), _prec(precision)
     if out is None:
         out = torch.empty((layer.din,) * 6, dtype=torch.float64, device=rho.device)
-    nb = _lib.mera_workspace_bytes(_lib.MERA_OP_DESCEND, layer.din, layer.dout, q, p)
-    ws, wsb = WORKSPACE.get(nb, rho.device)
+    ws, wsb = WORKSPACE.for_op(_lib.MERA_OP_DESCEND, layer.din, layer.dout, q, p, rho.device)
     _lib.check(_lib.mera_descend(layer.c(), rho.data_ptr(), out.data_ptr(), p, q, ws, wsb, _stream(rho.device)), "mera_descend")
     return out
 
@@ -106,8 +128,7 @@ def env_u(layer: Layer, h: torch.Tensor, rho: torch.Tensor, placement="avg", pre
     p, q = _place(placement), _prec(precision)
     if out is None:
         out = torch.empty((layer.din,) * 4, dtype=torch.float64, device=h.device)
-    nb = _lib.mera_workspace_bytes(_lib.MERA_OP_ENV_U, layer.din, layer.dout, q, p)
-    ws, wsb = WORKSPACE.get(nb, h.device)
+    ws, wsb = WORKSPACE.for_op(_lib.MERA_OP_ENV_U, layer.din, layer.dout, q, p, h.device)
     _lib.check(_lib.mera_env_u(layer.c(), h.data_ptr(), rho.data_ptr(), out.data_ptr(), p, q, ws, wsb, _stream(h.device)), "mera_env_u")
     return out
 
@@ -118,8 +139,7 @@ def env_w(layer: Layer, h: torch.Tensor, rho: torch.Tensor, placement="avg", pre
     p, q = _place(placement), _prec(precision)
     if out is None:
         out = torch.empty((layer.din, layer.din, layer.dout), dtype=torch.float64, device=h.device)
-    nb = _lib.mera_workspace_bytes(_lib.MERA_OP_ENV_W, layer.din, layer.dout, q, p)
-    ws, wsb = WORKSPACE.get(nb, h.device)
+    ws, wsb = WORKSPACE.for_op(_lib.MERA_OP_ENV_W, layer.din, layer.dout, q, p, h.device)
     _lib.check(_lib.mera_env_w(layer.c(), h.data_ptr(), rho.data_ptr(), out.data_ptr(), p, q, ws, wsb, _stream(h.device)), "mera_env_w")
     return out
 
@@ -153,8 +173,7 @@ def fixed_point_rho(si: Layer, rho: torch.Tensor, iters: int, precision="fp64", 
         raise ValueError("rho must be a contiguous float64 GPU tensor (it is updated in place)")
     q = _prec(precision)
     resid = torch.zeros(1, dtype=torch.float64, device=rho.device) if want_residual else None
-    nb = _lib.mera_workspace_bytes(_lib.MERA_OP_FIXED_POINT, si.din, si.dout, q, _lib.MERA_AVG)
-    ws, wsb = WORKSPACE.get(nb, rho.device)
+    ws, wsb = WORKSPACE.for_op(_lib.MERA_OP_FIXED_POINT, si.din, si.dout, q, _lib.MERA_AVG, rho.device)
     _lib.check(_lib.mera_fixed_point_rho(si.c(), rho.data_ptr(), int(iters), q,
                                          resid.data_ptr() if resid is not None else None,
                                          ws, wsb, _stream(rho.device)), "mera_fixed_point_rho")

@@ -122,7 +122,8 @@ def main(argv=None):
             e = float(ek.item()) + c
             dt = (time.perf_counter() - t0) / (k + 1 - start)
             rec = {"sweep": k + 1, "energy": e, "rel_error": (e - EXACT) / abs(EXACT), "s_per_sweep": dt,
-                   "chi": a.chi, "precision": a.precision}
+                   "chi": a.chi, "precision": a.precision,
+                   "peak_gb": round(torch.cuda.max_memory_allocated() / 1e9, 2)}
             line = json.dumps(rec)
             print(line, flush=True)
             if log:
