@@ -93,6 +93,33 @@ def cpu_baseline(chi: int, seed: int) -> dict:
                       f"(1/{chi} of a left-window descend, {flops:.3e} flop in the GPU schedule's count)"}
 
 
+def cpu_thread_scan(chi: int, seed: int) -> list:
+    """Oracle throughput on one host thread and on all of them (the same 1/chi slice of
+    D_L at a smaller chi, so that the single-thread run stays short)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import mera_oracle as O
+    from paper_1906_12030_amd import inputs as I
+    from paper_1906_12030_amd import ops
+
+    rng = np.random.default_rng(seed)
+    u, w = I.random_layer(rng, chi, chi)
+    g = rng.standard_normal((chi ** 3, 64))
+    rho = (g @ g.T) / np.trace(g @ g.T)
+    rho = rho.reshape((chi,) * 6)
+    flops = ops.flops("descend", chi, chi, "L") / chi
+    out = []
+    for threads in (1, os.cpu_count()):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            O.descend_placement_slice(u, w, rho, "L", 0)
+            dt = time.perf_counter() - t0
+        out.append({"threads": threads, "chi": chi, "seconds": round(dt, 3),
+                    "TFLOP/s": round(flops / dt / 1e12, 4)})
+    return out
+
+
 def traffic_probe(args):
     """Kernels for the FETCH_SIZE / WRITE_SIZE counter runs: one descend call in the
     benchmark precision (its chi^9 launches are the dominant kernel) and a plain
@@ -155,8 +182,9 @@ def main():
     t0 = time.perf_counter()
     e_mixed = None
     e_first = None
+    phases = {}
     for k in range(args.steps):
-        e, c = sweep.sweep(m, h1, shift, args.iters, prec)
+        e, c = sweep.sweep(m, h1, shift, args.iters, prec, timings=phases)
         e_mixed = e
         if k == 0:
             e_first = e
@@ -211,9 +239,12 @@ def main():
     print(f"# energy at final tensors: mixed {e_eval_mixed:.15f}  fp64 {e_eval_fp64:.15f}", file=sys.stderr, flush=True)
 
     cpu = None
+    scan = None
     if args.cpu_baseline:
         cpu = cpu_baseline(chi, args.seed)
         print(f"# cpu baseline: {cpu}", file=sys.stderr, flush=True)
+        scan = cpu_thread_scan(16, args.seed)
+        print(f"# oracle thread scan: {scan}", file=sys.stderr, flush=True)
 
     value = flops["total"] / t_mixed / 1e12
     roof_peak = PEAK["bf16"] / 3.0 if prec == "bf16x3" else PEAK[prec]
@@ -246,6 +277,7 @@ def main():
         "sweep_s_fp64": round(t_fp64, 4) if t_fp64 else None,
         "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3) if t_fp64 else None,
         "sweep_flops": flops,
+        "sweep_phase_s": {k: round(v / args.steps, 4) for k, v in phases.items()},
         "contraction_tflops_all_launches": round(all_f / (all_ms / 1e3) / 1e12, 3),
         "energy_after_mixed_sweeps": e_mixed,
         "energy_after_one_sweep_mixed": e_first,
@@ -263,6 +295,7 @@ def main():
                      "note": "split-bf16 peak = bf16 dense MFMA peak / 3 (three bf16 products per useful multiply-add)"
                      if prec == "bf16x3" else ""},
         "cpu_baseline": cpu,
+        "oracle_thread_scan": scan,
     }
     print(json.dumps(out))
 
