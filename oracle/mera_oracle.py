@@ -585,6 +585,71 @@ def ising_ground_energy_closed_form(nsite):
 
 
 # ---------------------------------------------------------------------------
+# Optimising the finite 16-site network (Fig. 1b; sweep order of Sec. II.C)
+# ---------------------------------------------------------------------------
+def finite_top_operator(h_top):
+    """Energy operator of the 4-site periodic top state: the average over the four
+    positions s of h_top acting on top sites (s, s+1, s+2) mod 4 (identity on the
+    fourth), as a d^4 x d^4 matrix, so that <top|H|top> = tr(h_top rho_top_avg)."""
+    d = h_top.shape[0]
+    n = d ** 4
+    hm = np.zeros((n, n))
+    eye = np.eye(d)
+    # operator on sites (0,1,2) of the ring, then cyclic shifts of the site order
+    h012 = np.einsum("abcABC,dD->abcdABCD", h_top, eye)
+    for s in range(4):
+        # move sites (0,1,2,3) of h012 to (s, s+1, s+2, s+3) mod 4
+        perm = [(k - s) % 4 for k in range(4)]
+        t = np.transpose(h012, perm + [4 + q for q in perm])
+        hm += t.reshape(n, n)
+    return hm / 4.0
+
+
+def finite_top_density(top):
+    """rho_top averaged over the four three-site windows of the top ring."""
+    return sum(top_density(top, s) for s in range(4)) / 4.0
+
+
+def finite_descend_chain(layers, top):
+    """[rho_1, ..., rho_{T+1}]: averaged window densities from the top state down."""
+    rhos = [finite_top_density(top)]
+    for u, w in reversed(layers):
+        rhos.insert(0, descend(u, w, rhos[0]))
+    return rhos
+
+
+def finite_energy(layers, top, h1, shift=0.0):
+    """Energy per site tr(h1 rho_1) (+ shift) of the finite network."""
+    return trace_product(h1, finite_descend_chain(layers, top)[0]) + shift
+
+
+def finite_sweep(layers, top, h1, shift=0.0):
+    """One sweep of the finite network, in the order of Sec. II.C with the top state in
+    place of the scale-invariant layer:
+      1. h_{t+1} = A_t(h_t) for every layer with the current tensors;
+      2. top <- lowest eigenvector of the top energy operator built from h_{T+1};
+      3. for t = T..1: u_t <- polar update of Env_u(h_t, rho_{t+1}); then w_t with the
+         new u_t; then rho_t = D_t(rho_{t+1}) with the new tensors;
+      4. the energy tr(h_1 rho_1) + shift.
+    Returns (layers, top, energy)."""
+    layers = [(u.copy(), w.copy()) for u, w in layers]
+    hs = [h1]
+    for u, w in layers:
+        hs.append(ascend(u, w, hs[-1]))
+    vals, vecs = np.linalg.eigh(finite_top_operator(hs[-1]))
+    d = hs[-1].shape[0]
+    top = vecs[:, 0].reshape((d,) * 4)
+    rho = finite_top_density(top)
+    for t in reversed(range(len(layers))):
+        u, w = layers[t]
+        u = update_u(env_u(u, w, hs[t], rho))
+        w = update_w(env_w(u, w, hs[t], rho))
+        layers[t] = (u, w)
+        rho = descend(u, w, rho)
+    return layers, top, trace_product(h1, rho) + shift
+
+
+# ---------------------------------------------------------------------------
 # Dense-matrix formulation of D (independent of the einsum network)
 # ---------------------------------------------------------------------------
 def descend_dense(u, w, rho):

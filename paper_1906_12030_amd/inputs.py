@@ -65,6 +65,18 @@ def init_mera(chi: int, n_transitional: int, seed: int):
     return layers, si
 
 
+def init_finite(chi: int, seed: int):
+    """Seeded 16-site network: layers (2 -> d2), (d2 -> d3) with d2 = min(chi, 4),
+    d3 = min(chi, d2^2), drawn bottom-up (u then w), then a unit-norm top state of
+    shape (d3,)*4 from standard_normal."""
+    rng = np.random.default_rng(seed)
+    d2 = min(chi, 4)
+    d3 = min(chi, d2 * d2)
+    layers = [random_layer(rng, 2, d2), random_layer(rng, d2, d3)]
+    top = rng.standard_normal((d3,) * 4)
+    return layers, top / np.linalg.norm(top)
+
+
 def random_density(rng: np.random.Generator, d: int, rank: int = 64) -> np.ndarray:
     """Positive semidefinite unit-trace three-site density: G G^T / tr, G in R^{d^3 x rank}."""
     n = d ** 3
