@@ -623,9 +623,10 @@ def finite_energy(layers, top, h1, shift=0.0):
     return trace_product(h1, finite_descend_chain(layers, top)[0]) + shift
 
 
-def finite_sweep(layers, top, h1, shift=0.0):
+def finite_sweep(layers, top, h1, shift=0.0, update_u_tensors=True):
     """One sweep of the finite network, in the order of Sec. II.C with the top state in
-    place of the scale-invariant layer:
+    place of the scale-invariant layer (update_u_tensors=False keeps the disentanglers
+    as given: with identity disentanglers this is the binary tree network of Fig. 1a):
       1. h_{t+1} = A_t(h_t) for every layer with the current tensors;
       2. top <- lowest eigenvector of the top energy operator built from h_{T+1};
       3. for t = T..1: u_t <- polar update of Env_u(h_t, rho_{t+1}); then w_t with the
@@ -642,7 +643,8 @@ def finite_sweep(layers, top, h1, shift=0.0):
     rho = finite_top_density(top)
     for t in reversed(range(len(layers))):
         u, w = layers[t]
-        u = update_u(env_u(u, w, hs[t], rho))
+        if update_u_tensors:
+            u = update_u(env_u(u, w, hs[t], rho))
         w = update_w(env_w(u, w, hs[t], rho))
         layers[t] = (u, w)
         rho = descend(u, w, rho)

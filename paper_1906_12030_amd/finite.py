@@ -1,4 +1,5 @@
-"""Finite periodic binary MERA on 16 sites (Fig. 1b) as an optimisation workload.
+"""Finite periodic binary MERA on 16 sites (Fig. 1b) as an optimisation workload, and
+the binary tree network (Fig. 1a) as its special case with identity disentanglers.
 
 Two layers (16 -> 8 -> 4 sites) under a 4-site periodic top state.  Each
 three-site window of the top ring has its own causal cone below it, so the
@@ -80,8 +81,9 @@ def energy(m: FiniteMera, h1: torch.Tensor, shift: float) -> float:
     return float(ops.energy(h1, descend_chain(m)[0]).item()) + shift
 
 
-def sweep(m: FiniteMera, h1: torch.Tensor, shift: float, precision="fp64") -> float:
-    """One sweep; returns the energy per site after it."""
+def sweep(m: FiniteMera, h1: torch.Tensor, shift: float, precision="fp64", disentangle=True) -> float:
+    """One sweep; returns the energy per site after it.  disentangle=False keeps the
+    disentanglers fixed (identity disentanglers: the binary tree network of Fig. 1a)."""
     hs = [h1]
     for t in range(len(m.layers)):
         hs.append(ops.ascend(m.layer(t), hs[-1], "avg", precision))
@@ -90,7 +92,8 @@ def sweep(m: FiniteMera, h1: torch.Tensor, shift: float, precision="fp64") -> fl
     m.top = vecs[:, 0].reshape((d,) * 4)
     rho = m.top_rho()
     for t in reversed(range(len(m.layers))):
-        m.layers[t][0] = ops.update_u(ops.env_u(m.layer(t), hs[t], rho, "avg", precision))
+        if disentangle:
+            m.layers[t][0] = ops.update_u(ops.env_u(m.layer(t), hs[t], rho, "avg", precision))
         m.layers[t][1] = ops.update_w(ops.env_w(m.layer(t), hs[t], rho, "avg", precision))
         rho = ops.descend(m.layer(t), rho, "avg", "fp64")
     return float(ops.energy(h1, rho).item()) + shift

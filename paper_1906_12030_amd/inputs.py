@@ -65,15 +65,19 @@ def init_mera(chi: int, n_transitional: int, seed: int):
     return layers, si
 
 
-def init_finite(chi: int, seed: int):
+def init_finite(chi: int, seed: int, tree: bool = False):
     """Seeded 16-site network: layers (2 -> d2), (d2 -> d3) with d2 = min(chi, 4),
     d3 = min(chi, d2^2), drawn bottom-up (u then w), then a unit-norm top state of
-    shape (d3,)*4 from standard_normal."""
+    shape (d3,)*4 from standard_normal.  tree=True replaces every disentangler by
+    the identity u[a,b,c,d] = delta_ac delta_bd (same draws, so the isometries and
+    the top state are those of the MERA start)."""
     rng = np.random.default_rng(seed)
     d2 = min(chi, 4)
     d3 = min(chi, d2 * d2)
     layers = [random_layer(rng, 2, d2), random_layer(rng, d2, d3)]
     top = rng.standard_normal((d3,) * 4)
+    if tree:
+        layers = [(np.eye(u.shape[0] ** 2).reshape(u.shape), w) for u, w in layers]
     return layers, top / np.linalg.norm(top)
 
 

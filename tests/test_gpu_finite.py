@@ -67,3 +67,26 @@ def test_finite_optimised_network_energy_is_its_state_energy(mods):
     assert abs(e_brute - es[-1]) < 1e-12
     assert es[-1] > finite.exact_energy_per_site()
     assert abs(finite.energy(m, h_g, c_g) - es[-1]) < 1e-13
+
+
+def test_tree_network_trajectory_matches_oracle(mods):
+    """Identity disentanglers kept fixed (binary tree network): GPU vs oracle sweeps.
+
+    Tolerance 1e-10: the isometry environments of the tree are less well conditioned
+    than the MERA's, so the polar factors of the GPU's Newton-Schulz iteration and the
+    oracle's SVD differ by a few 1e-12, which the following sweeps amplify (2e-11 after
+    three sweeps at seed 2)."""
+    finite, ops = mods
+    say("tree network trajectory chi=4")
+    layers, top = I.init_finite(4, 2, tree=True)
+    h_o, c_o = O.shifted_hamiltonian()
+    h_g, c_g = ops.tfim_hamiltonian(1.0)
+    m = finite.FiniteMera(layers, top)
+    ol, ot = layers, top
+    for k in range(6):
+        ol, ot, e_o = O.finite_sweep(ol, ot, h_o, c_o, update_u_tensors=False)
+        e_g = finite.sweep(m, h_g, c_g, disentangle=False)
+        assert abs(e_g - e_o) < 1e-10, (k, e_g, e_o)
+    for (ug, wg), (uo, wo) in zip(m.state_dict()["layers"], ol):
+        assert np.abs(ug - uo).max() == 0.0  # the identity, untouched
+        assert np.abs(wg - wo).max() < 1e-8

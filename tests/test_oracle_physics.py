@@ -111,3 +111,20 @@ def test_finite_host_helpers_match_oracle():
         assert np.abs(F.top_operator(h) - O.finite_top_operator(h)).max() < 1e-13
         assert np.abs(F.top_density(t) - O.finite_top_density(t)).max() < 1e-13
     assert abs(F.exact_energy_per_site(16) - O.ising_ground_energy_closed_form(16) / 16) < 1e-15
+
+
+def test_tree_network_sweeps():
+    """Binary tree network (identity disentanglers, never updated): the disentanglers stay
+    the identity, the energy drops and equals the explicit state's, and it stays above the
+    exact ground energy."""
+    h, c = O.shifted_hamiltonian()
+    lt, tt = I.init_finite(4, 0, tree=True)
+    es = []
+    for _ in range(25):
+        lt, tt, et = O.finite_sweep(lt, tt, h, c, update_u_tensors=False)
+        es.append(et)
+    for u, _ in lt:
+        assert np.abs(u.reshape(u.shape[0] ** 2, -1) - np.eye(u.shape[0] ** 2)).max() == 0.0
+    v = O.finite_state(lt, tt).reshape(-1)
+    assert abs(float(v @ (O.tfim_periodic_sparse(16) @ v)) / 16 - et) < 1e-12
+    assert es[-1] < es[0] and es[-1] > O.ising_ground_energy_closed_form(16) / 16
