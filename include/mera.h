@@ -181,6 +181,24 @@ int mera_profile_end(mera_profile_entry* out, int32_t max_entries, int32_t* n_ou
  * for the other ops.  Pure host function. */
 size_t mera_workspace_bytes_min(int op, int32_t din, int32_t dout, int precision, int placement);
 
+/* General contraction through the same engine as the calls above (diagnostic
+ * and test entry point): C[lc] = alpha * sum over the legs shared by A and B of
+ * A[la] * B[lb] + beta * C[lc].  la, lb, lc: leg labels (one character per leg,
+ * 1..6 legs each, no repeats within an operand); every output leg comes from
+ * exactly one operand and every summed leg appears in both (no batch legs).
+ * labels / sizes: the extent (1 .. 2^30) of every label used.  A, B, C: device
+ * float64, dense row-major in the order of their labels.  precision selects the
+ * internal arithmetic (MERA_FP64 / MERA_FP32 / MERA_BF16X3, operands converted in
+ * the workspace) and, through the shapes, the kernel (the large-tile split-bf16
+ * kernel takes operands contiguous along k with a k-run that is a multiple of
+ * 32, M >= 256, N >= 192).  Workspace: ws_bytes >= 8 (|A| + |B|) + 8 min(16 |C|,
+ * 2^24) + 1024 always suffices (MERA_EWORKSPACE with the exact need in
+ * mera_last_error otherwise).  Errors: MERA_EINVAL (null argument, precision),
+ * MERA_ESHAPE (labels, sizes; checked before any HIP call), MERA_EDEVICE.  Async. */
+int mera_contract(const char* la, const double* a_d, const char* lb, const double* b_d, const char* lc,
+                  double* c_d, const char* labels, const int64_t* sizes, double alpha, double beta,
+                  int precision, void* ws_d, size_t ws_bytes, void* hip_stream);
+
 /* Measured matrix-core throughput of this device in TFLOP/s, the peak the
  * contraction kernels are compared against: kind 0 = v_mfma_f32_16x16x32_bf16,
  * 1 = v_mfma_f32_16x16x4_f32, 2 = v_mfma_f64_16x16x4_f64, each with eight

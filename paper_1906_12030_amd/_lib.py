@@ -22,7 +22,7 @@ EXPORTED = (
     "mera_ascend", "mera_descend", "mera_env_u", "mera_env_w", "mera_polar_update",
     "mera_fixed_point_rho", "mera_energy", "mera_tfim_hamiltonian", "mera_workspace_bytes",
     "mera_strerror", "mera_last_error", "mera_flops", "mera_profile_begin", "mera_profile_end",
-    "mera_workspace_bytes_min", "mera_mfma_peak",
+    "mera_workspace_bytes_min", "mera_mfma_peak", "mera_contract",
 )
 
 
@@ -73,6 +73,9 @@ def load() -> ctypes.CDLL:
     lib.mera_strerror.restype = ctypes.c_char_p
     lib.mera_last_error.argtypes = []
     lib.mera_last_error.restype = ctypes.c_char_p
+    lib.mera_contract.argtypes = [ctypes.c_char_p, vp, ctypes.c_char_p, vp, ctypes.c_char_p, vp,
+                                  ctypes.c_char_p, ctypes.POINTER(i64), dbl, dbl, ctypes.c_int, vp, sz, vp]
+    lib.mera_contract.restype = ctypes.c_int
     lib.mera_mfma_peak.argtypes = [ctypes.c_int, vp, sz, ctypes.POINTER(dbl)]
     lib.mera_mfma_peak.restype = ctypes.c_int
     lib.mera_profile_begin.argtypes = []
@@ -141,6 +144,12 @@ def mera_workspace_bytes_min(op, din, dout, precision, placement):
 
 def mera_flops(op, din, dout, placement):
     return float(load().mera_flops(op, din, dout, placement))
+
+
+def mera_contract(la, a_ptr, lb, b_ptr, lc, c_ptr, labels, sizes, alpha, beta, precision, ws, ws_bytes, stream):
+    arr = (ctypes.c_int64 * len(sizes))(*sizes)
+    return load().mera_contract(la.encode(), a_ptr, lb.encode(), b_ptr, lc.encode(), c_ptr, labels.encode(),
+                                arr, alpha, beta, precision, ws, ws_bytes, stream)
 
 
 def mera_mfma_peak(kind, scratch_ptr, scratch_bytes):

@@ -357,6 +357,7 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
   if (!build_group(klab, la, lb, dims, dims, args.gk, K)) return hipErrorInvalidValue;
   if (flops) *flops += 2.0 * (double)M * (double)N * (double)K;
   if (M == 0 || N == 0) return hipSuccess;
+  if (K == 0) return hipErrorInvalidValue;  // the kernels assume at least one k-tile
   args.a = A;
   args.b = B;
   args.c = C;

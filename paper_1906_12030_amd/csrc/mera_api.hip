@@ -570,6 +570,86 @@ int mera_profile_end(mera_profile_entry* out, int32_t max_entries, int32_t* n_ou
   return rc;
 }
 
+int mera_contract(const char* la, const double* a_d, const char* lb, const double* b_d, const char* lc,
+                  double* c_d, const char* labels, const int64_t* sizes, double alpha, double beta,
+                  int precision, void* ws_d, size_t ws_bytes, void* hip_stream) {
+  if (!la || !lb || !lc || !labels || !sizes || !a_d || !b_d || !c_d) {
+    set_err("mera_contract: null argument");
+    return MERA_EINVAL;
+  }
+  if (precision < MERA_FP64 || precision > MERA_BF16X3) {
+    set_err("mera_contract: precision out of range");
+    return MERA_EINVAL;
+  }
+  // labels: distinct printable characters with sizes >= 1
+  LabelDims dims;
+  std::string seen;
+  for (const char* q = labels; *q; ++q) {
+    const unsigned char ch = (unsigned char)*q;
+    if (ch < 33 || ch > 126 || seen.find((char)ch) != std::string::npos || sizes[q - labels] < 1 ||
+        sizes[q - labels] > (int64_t)1 << 30) {
+      set_err("mera_contract: labels must be distinct printable characters with sizes in [1, 2^30]");
+      return MERA_ESHAPE;
+    }
+    seen.push_back((char)ch);
+    dims.d[ch] = sizes[q - labels];
+  }
+  const std::string sa(la), sb(lb), sc(lc);
+  auto has = [](const std::string& s, char ch) { return s.find(ch) != std::string::npos; };
+  auto count_of = [&](const std::string& s) -> int64_t {
+    int64_t n = 1;
+    for (char ch : s) n *= dims.d[(unsigned char)ch];
+    return n;
+  };
+  // every leg known and not repeated; each output leg in exactly one operand; summed legs in both
+  for (const std::string* s : {&sa, &sb, &sc}) {
+    if (s->empty() || s->size() > 6) {
+      set_err("mera_contract: each operand needs 1..6 legs");
+      return MERA_ESHAPE;
+    }
+    for (size_t i = 0; i < s->size(); ++i)
+      if (!has(seen, (*s)[i]) || s->find((*s)[i], i + 1) != std::string::npos) {
+        set_err("mera_contract: unknown or repeated leg label");
+        return MERA_ESHAPE;
+      }
+  }
+  int64_t M = 1, N = 1, K = 1;
+  for (char ch : sc) {
+    if (has(sa, ch) == has(sb, ch)) {
+      set_err("mera_contract: an output leg must come from exactly one operand");
+      return MERA_ESHAPE;
+    }
+    (has(sa, ch) ? M : N) *= dims.d[(unsigned char)ch];
+  }
+  for (char ch : sa)
+    if (!has(sc, ch)) {
+      if (!has(sb, ch)) {
+        set_err("mera_contract: a summed leg must appear in both operands");
+        return MERA_ESHAPE;
+      }
+      K *= dims.d[(unsigned char)ch];
+    }
+  for (char ch : sb)
+    if (!has(sc, ch) && !has(sa, ch)) {
+      set_err("mera_contract: a summed leg must appear in both operands");
+      return MERA_ESHAPE;
+    }
+  if (M >= ((int64_t)1 << 31) || N >= ((int64_t)1 << 31) || K >= ((int64_t)1 << 31)) {
+    set_err("mera_contract: M, N and K must each stay below 2^31");
+    return MERA_ESHAPE;
+  }
+  Ctx cx;
+  cx.ar = arith_of(precision);
+  return run_checked(cx, ws_d, ws_bytes, hip_stream, [&](Ctx& c) {
+    c.dims = dims;
+    c.scratch_elems = (size_t)std::min<int64_t>(16 * M * N, (int64_t)1 << 24);
+    c.scratch = c.take_d(c.scratch_elems);
+    const void* a = working_op(c, a_d, count_of(sa));
+    const void* b = working_op(c, b_d, count_of(sb));
+    c.c(a, la, b, lb, c_d, lc, true, alpha, beta);
+  });
+}
+
 int mera_mfma_peak(int kind, void* scratch_d, size_t scratch_bytes, double* tflops_out) {
   // 2048 workgroups x 4 waves = 8 waves per SIMD on 256 CUs; about 5 ms per launch
   constexpr int kBlocks = 2048;

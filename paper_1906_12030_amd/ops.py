@@ -212,3 +212,29 @@ def mfma_peak(kind: str = "bf16") -> float:
     st, tf = _lib.mera_mfma_peak(k, scratch.data_ptr(), scratch.numel() * 4)
     _lib.check(st, "mera_mfma_peak")
     return tf
+
+
+def contract(spec: str, a: torch.Tensor, b: torch.Tensor, precision="fp64", alpha=1.0, beta=0.0,
+             out: torch.Tensor | None = None) -> torch.Tensor:
+    """C = alpha * einsum(spec, a, b) + beta * C through the library's contraction engine
+    (spec "ab,bc->ac"; one character per leg; no batch legs)."""
+    a, b = _dev(a), _dev(b)
+    lhs, lc = spec.replace(" ", "").split("->")
+    la, lb = lhs.split(",")
+    size = {}
+    for lab, t in ((la, a), (lb, b)):
+        if len(lab) != t.dim():
+            raise ValueError(f"{lab!r} does not match a tensor of rank {t.dim()}")
+        for ch, n in zip(lab, t.shape):
+            if size.setdefault(ch, int(n)) != int(n):
+                raise ValueError(f"leg {ch!r} has two sizes")
+    labels = "".join(size)
+    if out is None:
+        out = torch.zeros([size[ch] for ch in lc], dtype=torch.float64, device=a.device)
+    na, nb, nc = a.numel(), b.numel(), out.numel()
+    need = 8 * (na + nb) + 8 * min(16 * nc, 1 << 24) + 4096
+    ws, wsb = WORKSPACE.get(need, a.device)
+    _lib.check(_lib.mera_contract(la, a.data_ptr(), lb, b.data_ptr(), lc, out.data_ptr(), labels,
+                                  [size[ch] for ch in labels], float(alpha), float(beta), _prec(precision),
+                                  ws, wsb, _stream(a.device)), "mera_contract")
+    return out

@@ -139,3 +139,21 @@ def test_mfma_peak_argument_checks(lib):
     assert st == _lib.MERA_EINVAL
     st, _ = _lib.mera_mfma_peak(0, fake, 1 << 20)
     assert st == _lib.MERA_EWORKSPACE
+
+
+def test_contract_argument_checks(lib):
+    """mera_contract rejects malformed specifications before any HIP call."""
+    fake = 4096
+    ok = dict(a=fake, b=fake, c=fake, ws=fake, wsb=1 << 30)
+
+    def call(la, lb, lc, labels, sizes, prec=0):
+        return _lib.mera_contract(la, ok["a"], lb, ok["b"], lc, ok["c"], labels, sizes, 1.0, 0.0, prec,
+                                  ok["ws"], ok["wsb"], None)
+    assert call("ab", "bc", "ac", "abc", [2, 3, 4], prec=7) == _lib.MERA_EINVAL
+    assert call("ab", "bc", "ac", "abc", [2, 0, 4]) == _lib.MERA_ESHAPE      # empty leg
+    assert call("ab", "bc", "ac", "abb", [2, 3, 4]) == _lib.MERA_ESHAPE      # repeated label
+    assert call("aab", "bc", "ac", "abc", [2, 3, 4]) == _lib.MERA_ESHAPE     # repeated leg
+    assert call("ab", "bc", "abc", "abc", [2, 3, 4]) == _lib.MERA_ESHAPE     # batch leg b
+    assert call("ab", "cd", "ac", "abcd", [2, 3, 4, 5]) == _lib.MERA_ESHAPE  # b, d summed in one operand
+    assert call("ab", "bc", "ax", "abc", [2, 3, 4]) == _lib.MERA_ESHAPE      # unknown label
+    assert call("ab", "bc", "ac", "abc", [1 << 31, 3, 4]) == _lib.MERA_ESHAPE
