@@ -13,8 +13,10 @@ namespace mera {
 // Arithmetic of one contraction.
 //   F64: double operands, FP64 MFMA (v_mfma_f64_16x16x4f64).
 //   F32: float operands, FP32 MFMA (v_mfma_f32_16x16x4f32).
-//   B3 : float operands split on load into bf16 hi + lo, three BF16 MFMA
-//        products (hi*hi + hi*lo + lo*hi) accumulated in FP32.
+//   B3 : operands and FP32 intermediates stored as split words (bf16 hi of
+//        the FP32 value in the upper half, bf16 lo of the remainder in the lower
+//        half; see pack_split in tc_common.h), three BF16 MFMA products
+//        (hi*hi + hi*lo + lo*hi) accumulated in FP32.
 enum class Arith : int { F64 = 0, F32 = 1, B3 = 2 };
 
 // Sizes of the index labels used by contraction specs (one char per label).
@@ -31,8 +33,9 @@ struct LabelDims {
 // C[lc] = alpha * sum_{shared labels} A[la] * B[lb] + beta * C[lc].
 // Each operand is dense row-major in the order of its label string.  Labels
 // shared by A and B and absent from C are summed; labels of C come from exactly
-// one of A and B.  A and B hold double for F64 and float otherwise; C holds
-// double when c_f64 and float otherwise.  Returns hipSuccess or the launch
+// one of A and B.  A and B hold double for F64, float for F32 and split words
+// for B3; C holds double when c_f64 and otherwise float (F32) or split words
+// (B3).  K must be at least 1.  Returns hipSuccess or the launch
 // error.  `flops` (nullable) is increased by 2*M*N*K.  `scratch` (device,
 // nullable) of scratch_elems doubles lets the engine split long k ranges over
 // several workgroups (partial sums reduced in a fixed order) when the output
