@@ -43,6 +43,52 @@ PEAK = {  # MI355X published dense peaks, TFLOP/s
 }
 
 
+def env_rates(recs, code, ops, lib):
+    """Environment contraction launches (mera_env_u / mera_env_w) of the timed sweeps."""
+    env_ops = (lib.MERA_OP_ENV_U, lib.MERA_OP_ENV_W)
+    sel = [r for r in recs if r[4] in env_ops and r[1] == code]
+    if not sel:
+        return None
+    f = sum(r[2] for r in sel)
+    ms = sum(r[3] for r in sel)
+    tf = f / (ms / 1e3) / 1e12
+    return {"launches": len(sel), "flops": f, "launch_ms": round(ms, 3), "tflops": round(tf, 3),
+            "frac_of_fp32_mfma_peak": round(tf / PEAK["fp32"], 4)}
+
+
+def env_call_rates(m, h1, precision, ops, sweep, lib):
+    """One mera_env_u and one mera_env_w call on the scale-invariant layer at the
+    current tensors: whole-call time (HIP events on the stream, conversions included)
+    and the contraction launches inside, against the FP32 MFMA peak."""
+    import torch
+
+    h = sweep.ascend_chain(m, h1, "fp64")[-1]
+    si = m.si_layer()
+    d = si.din
+    torch.cuda.synchronize()
+    out = {"precision": precision}
+    tot_f, tot_s = 0.0, 0.0
+    for name, fn in (("env_u", ops.env_u), ("env_w", ops.env_w)):
+        lib.mera_profile_begin()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn(si, h, m.rho_star, "avg", precision)
+        b.record()
+        torch.cuda.synchronize()
+        _, recs = lib.mera_profile_end()
+        f = ops.flops(name, d, d)
+        s_call = a.elapsed_time(b) / 1e3
+        s_launch = sum(r[3] for r in recs) / 1e3
+        out[name] = {"flops": f, "call_ms": round(1e3 * s_call, 3), "call_tflops": round(f / s_call / 1e12, 3),
+                     "launch_tflops": round(f / s_launch / 1e12, 3)}
+        tot_f += f
+        tot_s += s_call
+    out["call_tflops"] = round(tot_f / tot_s / 1e12, 3)
+    out["frac_of_fp32_mfma_peak"] = round(tot_f / tot_s / 1e12 / PEAK["fp32"], 4)
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +254,20 @@ def main():
     all_ms = sum(r[3] for r in recs)
     all_f = sum(r[2] for r in recs)
 
+    env = env_rates(recs, code, ops, _lib)
+    # per-step totals of the timed sweeps (stderr only)
+    steps = {}
+    for r in recs:
+        e = steps.setdefault((r[0], r[1], r[4]), [0, 0.0, 0.0])
+        e[0] += 1
+        e[1] += r[3]
+        e[2] += r[2]
+    print("# top contraction steps over the timed sweeps (labels, arith, op): count, total ms, TFLOP/s",
+          file=sys.stderr)
+    for (lab, ar, op), (n, ms, f) in sorted(steps.items(), key=lambda kv: -kv[1][1])[:30]:
+        print(f"#   {lab:28s} a={ar} op={op} {n:5d} {ms:10.2f} {f / (ms / 1e3) / 1e12:8.1f}", file=sys.stderr)
+    sys.stderr.flush()
+
     # ---- plain FP64 sweep(s) from the same starting state, for the ratio ----
     t_fp64 = None
     e_fp64 = None
@@ -237,6 +297,9 @@ def main():
     # both evaluations: rho* by args.iters steps from the same warm start (the
     # mixed one in FP64 iterative-refinement form), FP64 descent and trace
     print(f"# energy at final tensors: mixed {e_eval_mixed:.15f}  fp64 {e_eval_fp64:.15f}", file=sys.stderr, flush=True)
+
+    env_fp32 = env_call_rates(m, h1, "fp32", ops, sweep, _lib)
+    print(f"# environment calls in fp32: {env_fp32}", file=sys.stderr, flush=True)
 
     cpu = None
     scan = None
@@ -279,6 +342,8 @@ def main():
         "sweep_flops": flops,
         "sweep_phase_s": {k: round(v / args.steps, 4) for k, v in phases.items()},
         "contraction_tflops_all_launches": round(all_f / (all_ms / 1e3) / 1e12, 3),
+        "env_contraction": env,
+        "env_contraction_fp32": env_fp32,
         "energy_after_mixed_sweeps": e_mixed,
         "energy_after_one_sweep_mixed": e_first,
         "energy_after_one_sweep_fp64": e_fp64,

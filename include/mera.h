@@ -167,6 +167,7 @@ size_t mera_workspace_bytes(int op, int32_t din, int32_t dout, int precision, in
 typedef struct {
   char step[48];    /* "la,lb->lc" leg labels of the contraction */
   int32_t arith;    /* mera_precision of the launch */
+  int32_t op;       /* mera_op of the call that issued it; -1 for mera_contract */
   double flops;     /* 2*M*N*K of the launch */
   double ms;        /* device time between the two events */
 } mera_profile_entry;
@@ -220,6 +221,19 @@ const char* mera_last_error(void);
 /* Double-precision flops of the schedule executed by `op` (multiply-add = 2),
  * for throughput accounting; 0 for invalid arguments.  Pure host function. */
 double mera_flops(int op, int32_t din, int32_t dout, int placement);
+
+/* Diagnostic: the contraction schedule of `op` (ascend, descend, env_u,
+ * env_w, or one fixed-point iteration) for these sizes, one line per
+ * contraction, "la,lb->lc <kernel> m=M n=N k=K tiles=TMxTN splits=S store=..."
+ * with <kernel> one of f64, f32, b3 (128 x 128 split-bf16 kernel) and b3x192
+ * / b3x256 (large-tile split-bf16 kernel), and store= n4 / n1 (vector /
+ * element stores along the output's n legs) or m4 / m1 (along its m legs).
+ * Writes at most out_bytes bytes (NUL-terminated) into out (host memory,
+ * nullable) and the full size including the NUL into *needed (nullable).
+ * The unsliced schedule, with the full workspace.  Returns MERA_EINVAL /
+ * MERA_ESHAPE for bad arguments.  Pure host function. */
+int mera_schedule_plan(int op, int32_t din, int32_t dout, int precision, int placement, char* out,
+                       size_t out_bytes, size_t* needed);
 
 #ifdef __cplusplus
 }

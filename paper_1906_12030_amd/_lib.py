@@ -22,7 +22,7 @@ EXPORTED = (
     "mera_ascend", "mera_descend", "mera_env_u", "mera_env_w", "mera_polar_update",
     "mera_fixed_point_rho", "mera_energy", "mera_tfim_hamiltonian", "mera_workspace_bytes",
     "mera_strerror", "mera_last_error", "mera_flops", "mera_profile_begin", "mera_profile_end",
-    "mera_workspace_bytes_min", "mera_mfma_peak", "mera_contract",
+    "mera_workspace_bytes_min", "mera_mfma_peak", "mera_contract", "mera_schedule_plan",
 )
 
 
@@ -32,7 +32,7 @@ class MeraLayer(ctypes.Structure):
 
 
 class MeraProfileEntry(ctypes.Structure):
-    _fields_ = [("step", ctypes.c_char * 48), ("arith", ctypes.c_int32),
+    _fields_ = [("step", ctypes.c_char * 48), ("arith", ctypes.c_int32), ("op", ctypes.c_int32),
                 ("flops", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
@@ -78,6 +78,9 @@ def load() -> ctypes.CDLL:
     lib.mera_contract.restype = ctypes.c_int
     lib.mera_mfma_peak.argtypes = [ctypes.c_int, vp, sz, ctypes.POINTER(dbl)]
     lib.mera_mfma_peak.restype = ctypes.c_int
+    lib.mera_schedule_plan.argtypes = [ctypes.c_int, i32, i32, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, sz,
+                                       ctypes.POINTER(sz)]
+    lib.mera_schedule_plan.restype = ctypes.c_int
     lib.mera_profile_begin.argtypes = []
     lib.mera_profile_begin.restype = ctypes.c_int
     lib.mera_profile_end.argtypes = [ctypes.POINTER(MeraProfileEntry), i32, ctypes.POINTER(i32)]
@@ -167,5 +170,17 @@ def mera_profile_end(max_entries=200000):
     buf = (MeraProfileEntry * max_entries)()
     n = ctypes.c_int32(0)
     st = load().mera_profile_end(buf, max_entries, ctypes.byref(n))
-    return st, [(buf[i].step.decode(), int(buf[i].arith), float(buf[i].flops), float(buf[i].ms))
-                for i in range(n.value)]
+    return st, [(buf[i].step.decode(), int(buf[i].arith), float(buf[i].flops), float(buf[i].ms),
+                 int(buf[i].op)) for i in range(n.value)]
+
+
+def mera_schedule_plan(op, din, dout, precision, placement):
+    """(status, [lines]) of the contraction schedule with the kernel chosen for each step."""
+    need = ctypes.c_size_t(0)
+    lib = load()
+    st = lib.mera_schedule_plan(op, din, dout, precision, placement, None, 0, ctypes.byref(need))
+    if st != MERA_OK:
+        return st, []
+    buf = ctypes.create_string_buffer(need.value)
+    st = lib.mera_schedule_plan(op, din, dout, precision, placement, buf, need.value, None)
+    return st, [ln for ln in buf.value.decode().split("\n") if ln]

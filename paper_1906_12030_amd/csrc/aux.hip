@@ -30,6 +30,39 @@ __global__ void k_to_split(const double* __restrict__ x, uint32_t* __restrict__ 
     y[i] = pack_split((float)x[i]);
 }
 
+// Split words of a d^6 density x[i j k I J K] written as y[j k J K i I]: a
+// transpose of the d^2 x d^4 matrix (rows (i, I), columns (j, k, J, K)) in
+// 64 x 64 tiles through LDS, so that the loads run along the columns (the
+// innermost J K of x) and the stores along the rows (the innermost i I of y).
+__global__ __launch_bounds__(256) void k_rho_to_split_perm(const double* __restrict__ x,
+                                                           uint32_t* __restrict__ y, int32_t d) {
+  __shared__ uint32_t t[64][65];
+  const int64_t d2 = (int64_t)d * d, d3 = d2 * d, d4 = d3 * d, d5 = d4 * d;
+  const int64_t c0 = (int64_t)blockIdx.x * 64;
+  const int64_t r0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t c = c0 + tx;
+  if (c < d4) {
+    const int64_t coff = (c / d2) * d3 + c % d2;
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {
+      const int rl = ty + 4 * q;
+      const int64_t r = r0 + rl;
+      if (r < d2) t[rl][tx] = pack_split((float)x[(r / d) * d5 + (r % d) * d2 + coff]);
+    }
+  }
+  __syncthreads();
+  const int64_t r = r0 + tx;
+  if (r < d2) {
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {
+      const int cl = ty + 4 * q;
+      const int64_t cc = c0 + cl;
+      if (cc < d4) y[cc * d2 + r] = t[tx][cl];
+    }
+  }
+}
+
 __global__ void k_scale(const double* __restrict__ x, double* __restrict__ y, double a, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -164,6 +197,12 @@ hipError_t launch_to_f32(const double* x, float* y, int64_t n, bool split, hipSt
                        reinterpret_cast<uint32_t*>(y), n);
   else
     hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
+  return hipGetLastError();
+}
+hipError_t launch_rho_to_split_perm(const double* x, float* y, int32_t d, hipStream_t s) {
+  const int64_t d2 = (int64_t)d * d;
+  const dim3 grid((unsigned)((d2 * d2 + 63) / 64), (unsigned)((d2 + 63) / 64));
+  hipLaunchKernelGGL(k_rho_to_split_perm, grid, dim3(256), 0, s, x, reinterpret_cast<uint32_t*>(y), d);
   return hipGetLastError();
 }
 hipError_t launch_scale(const double* x, double* y, double a, int64_t n, hipStream_t s) {

@@ -187,11 +187,6 @@ __global__ __launch_bounds__(256) void tc_splitk_reduce(TcArgs p) {
 // ---------------------------------------------------------------------------
 namespace {
 
-struct Plan {
-  std::string mlab, nlab, klab;  // group legs, outer..inner
-  bool swapped = false;
-};
-
 int64_t stride_in(const std::string& lab, char c, const LabelDims& dims) {
   int64_t s = 1;
   for (int i = (int)lab.size() - 1; i >= 0; --i) {
@@ -308,17 +303,25 @@ double contract_flops(const LabelDims& dims, const char* la_, const char* lb_, c
   return f;
 }
 
-hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* la_, const void* B,
-                    const char* lb_, void* C, const char* lc_, bool c_f64, double alpha,
-                    double beta, hipStream_t stream, double* flops, double* scratch,
-                    size_t scratch_elems, const LabelDims* cdims) {
-  const LabelDims& cd = cdims ? *cdims : dims;
-  std::string la(la_), lb(lb_), lc(lc_);
-  // C's innermost leg must come from "B" so that stores run along n.
-  if (!lc.empty() && contains(la, lc.back()) && !contains(lb, lc.back())) {
-    std::swap(la, lb);
-    std::swap(A, B);
-  }
+namespace {
+
+// Kernel choice and arguments of one contraction, A on the m side and B on
+// the n side.
+struct Plan {
+  TcArgs args;
+  int64_t M = 0, N = 0, K = 0;
+  bool A_KC = false, va = false, B_NC = false, vb = false, kal = false;
+  bool use_x = false;
+  int xbn = 0;
+};
+
+// Plans C[lc] = A[la] . B[lb].  `m_store`: C's innermost leg is an m leg,
+// which only the large-tile kernel stores efficiently (pl.use_x says whether
+// it was chosen).  Stops after the group sizes when M, N or K is zero.
+hipError_t make_plan(Arith ar, const LabelDims& dims, const LabelDims& cd, const void* A,
+                     const std::string& la, const void* B, const std::string& lb, void* C,
+                     const std::string& lc, bool c_f64, double alpha, double beta, double* scratch,
+                     size_t scratch_elems, bool m_store, Plan& pl) {
   std::string mlab, nlab, klab;
   for (char c : lc) {
     const bool ia = contains(la, c), ib = contains(lb, c);
@@ -332,9 +335,10 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
   }
   for (char c : lb)
     if (!contains(lc, c) && !contains(la, c)) return hipErrorInvalidValue;
-  // order m legs as in A when A's innermost leg is an m leg (loads along m)
+  // order m legs as in A when A's innermost leg is an m leg (loads along m);
+  // otherwise they keep C's order
   const bool a_last_m = !la.empty() && contains(mlab, la.back());
-  if (a_last_m) {
+  if (a_last_m && !m_store) {
     std::string o;
     for (char c : la)
       if (contains(mlab, c)) o.push_back(c);
@@ -349,15 +353,13 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
       if (contains(klab, c)) o.push_back(c);
     klab = o;
   }
-  TcArgs args;
+  TcArgs& args = pl.args;
   std::memset(&args, 0, sizeof(args));
-  int64_t M, N, K;
-  if (!build_group(mlab, la, lc, dims, cd, args.gm, M)) return hipErrorInvalidValue;
-  if (!build_group(nlab, lb, lc, dims, cd, args.gn, N)) return hipErrorInvalidValue;
-  if (!build_group(klab, la, lb, dims, dims, args.gk, K)) return hipErrorInvalidValue;
-  if (flops) *flops += 2.0 * (double)M * (double)N * (double)K;
-  if (M == 0 || N == 0) return hipSuccess;
-  if (K == 0) return hipErrorInvalidValue;  // the kernels assume at least one k-tile
+  if (!build_group(mlab, la, lc, dims, cd, args.gm, pl.M)) return hipErrorInvalidValue;
+  if (!build_group(nlab, lb, lc, dims, cd, args.gn, pl.N)) return hipErrorInvalidValue;
+  if (!build_group(klab, la, lb, dims, dims, args.gk, pl.K)) return hipErrorInvalidValue;
+  const int64_t M = pl.M, N = pl.N, K = pl.K;
+  if (M == 0 || N == 0 || K == 0) return hipSuccess;
   args.a = A;
   args.b = B;
   args.c = C;
@@ -375,24 +377,24 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
   const bool bkc = b_last_k && args.gk.sy[args.gk.nd - 1] == 1;
   const int elem = (ar == Arith::F64) ? 8 : 4;
   const int W = 16 / elem;
-  bool A_KC = akc || !amc;  // generic layouts fall back to element loads along k
-  bool B_NC = bnc || !bkc;
-  bool va = A_KC ? (akc && vec_ok(la, la.back(), dims, W) && args.gk.size[args.gk.nd - 1] % W == 0)
-                 : (vec_ok(la, la.back(), dims, W) && args.gm.size[args.gm.nd - 1] % W == 0);
-  bool vb = B_NC ? (bnc && vec_ok(lb, lb.back(), dims, W) && args.gn.size[args.gn.nd - 1] % W == 0)
-                 : (vec_ok(lb, lb.back(), dims, W) && args.gk.size[args.gk.nd - 1] % W == 0);
-  if (reinterpret_cast<uintptr_t>(A) % 16) va = false;
-  if (reinterpret_cast<uintptr_t>(B) % 16) vb = false;
+  pl.A_KC = akc || !amc;  // generic layouts fall back to element loads along k
+  pl.B_NC = bnc || !bkc;
+  pl.va = pl.A_KC ? (akc && vec_ok(la, la.back(), dims, W) && args.gk.size[args.gk.nd - 1] % W == 0)
+                  : (vec_ok(la, la.back(), dims, W) && args.gm.size[args.gm.nd - 1] % W == 0);
+  pl.vb = pl.B_NC ? (bnc && vec_ok(lb, lb.back(), dims, W) && args.gn.size[args.gn.nd - 1] % W == 0)
+                  : (vec_ok(lb, lb.back(), dims, W) && args.gk.size[args.gk.nd - 1] % W == 0);
+  if (reinterpret_cast<uintptr_t>(A) % 16) pl.va = false;
+  if (reinterpret_cast<uintptr_t>(B) % 16) pl.vb = false;
   // k-aligned tiles: the innermost k leg's extent is a multiple of the k-tile
   const int bk = (ar == Arith::B3) ? 32 : 16;
-  const bool kal = args.gk.size[args.gk.nd - 1] % bk == 0;
-  if (!kal) va = vb = false;
+  pl.kal = args.gk.size[args.gk.nd - 1] % bk == 0;
+  if (!pl.kal) pl.va = pl.vb = false;
   // Split-bf16 contractions whose operands are both contiguous along k go to
   // the large-tile kernel with direct-to-LDS loads (contract_b3x.hip).
-  int xbn = 0;
-  const bool use_x = ar == Arith::B3 && kal && akc && va && bkc && !bnc && vb &&
-                     contract_b3x_fits(M, N, xbn);
-  const int64_t tbm = use_x ? 256 : kBM, tbn = use_x ? xbn : kBN;
+  pl.use_x = ar == Arith::B3 && pl.kal && akc && pl.va && bkc && !bnc && pl.vb &&
+             contract_b3x_fits(M, N, pl.xbn);
+  if (m_store && !pl.use_x) return hipSuccess;  // the caller plans the swapped order
+  const int64_t tbm = pl.use_x ? 256 : kBM, tbn = pl.use_x ? pl.xbn : kBN;
   args.tiles_m = (int32_t)((M + tbm - 1) / tbm);
   args.tiles_n = (int32_t)((N + tbn - 1) / tbn);
   const int64_t tiles = (int64_t)args.tiles_m * args.tiles_n;
@@ -403,7 +405,7 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
   int splits = 1;
   int64_t kchunk = ((K + bk - 1) / bk) * bk;
   if (scratch && scratch_elems > 0) {
-    const double kSlots = use_x ? 256.0 : 512.0;
+    const double kSlots = pl.use_x ? 256.0 : 512.0;
     auto fill = [&](int64_t n) { return (double)n / (std::ceil((double)n / kSlots) * kSlots); };
     double best = fill(tiles);
     for (int s = 2; s <= 16; ++s) {
@@ -429,24 +431,108 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
                  reinterpret_cast<uintptr_t>(C) % 16 == 0)
                     ? 1
                     : 0;
+  if (pl.use_x) {
+    // the large-tile kernel stores 4 consecutive columns (a multiple of 4
+    // from the tile start) as one vector
+    if (splits > 1) {
+      args.cvec = (N % 4 == 0) ? 1 : 0;
+    } else {
+      bool nv = args.gn.sy[args.gn.nd - 1] == 1 && args.gn.size[args.gn.nd - 1] % 4 == 0 &&
+                reinterpret_cast<uintptr_t>(C) % 16 == 0;
+      for (int d = 0; d < args.gn.nd - 1; ++d) nv = nv && args.gn.sy[d] % 4 == 0;
+      for (int d = 0; d < args.gm.nd; ++d) nv = nv && args.gm.sy[d] % 4 == 0;
+      args.cvec = nv ? 1 : 0;
+    }
+  }
+  if (m_store) {
+    // four consecutive rows (a multiple of 4 apart from the tile start) are
+    // adjacent and 16-byte aligned in C
+    bool mv = args.gm.sy[args.gm.nd - 1] == 1 && args.gm.size[args.gm.nd - 1] % 4 == 0 &&
+              reinterpret_cast<uintptr_t>(C) % 16 == 0;
+    for (int d = 0; d < args.gm.nd - 1; ++d) mv = mv && args.gm.sy[d] % 4 == 0;
+    for (int d = 0; d < args.gn.nd; ++d) mv = mv && args.gn.sy[d] % 4 == 0;
+    args.cm = mv ? 1 : 2;
+  }
   args.per_xcd = (int32_t)((tiles * splits + 7) / 8);
   args.group_m = 8;
+  return hipSuccess;
+}
+
+// Operand order and plan: the general kernels store along n, so C's innermost
+// leg must come from "B"; the large-tile split-bf16 kernel also stores along
+// m and then takes the operands in the given order (A = m side).
+hipError_t choose_plan(Arith ar, const LabelDims& dims, const LabelDims& cd, const void* A,
+                       const char* la_, const void* B, const char* lb_, void* C, const char* lc_,
+                       bool c_f64, double alpha, double beta, double* scratch,
+                       size_t scratch_elems, Plan& pl) {
+  std::string la(la_), lb(lb_), lc(lc_);
+  const bool c_from_a = !lc.empty() && contains(la, lc.back()) && !contains(lb, lc.back());
+  if (c_from_a && ar == Arith::B3) {
+    const hipError_t e = make_plan(ar, dims, cd, A, la, B, lb, C, lc, c_f64, alpha, beta, scratch,
+                                   scratch_elems, true, pl);
+    if (e != hipSuccess) return e;
+    if (pl.use_x || pl.M == 0 || pl.N == 0 || pl.K == 0) return hipSuccess;
+  }
+  if (c_from_a) {
+    std::swap(la, lb);
+    std::swap(A, B);
+  }
+  pl = Plan();
+  return make_plan(ar, dims, cd, A, la, B, lb, C, lc, c_f64, alpha, beta, scratch, scratch_elems,
+                   false, pl);
+}
+
+}  // namespace
+
+std::string contract_plan(Arith ar, const LabelDims& dims, const char* la, const char* lb,
+                          const char* lc, bool c_f64, size_t scratch_elems,
+                          const LabelDims* cdims) {
+  // host-only: aligned placeholder addresses, never dereferenced
+  void* const fake = reinterpret_cast<void*>(uintptr_t(1) << 20);
+  Plan pl;
+  if (choose_plan(ar, dims, cdims ? *cdims : dims, fake, la, fake, lb, fake, lc, c_f64, 1.0, 0.0,
+                  scratch_elems ? static_cast<double*>(fake) : nullptr, scratch_elems,
+                  pl) != hipSuccess)
+    return "unsupported";
+  char buf[160];
+  const TcArgs& a = pl.args;
+  const char* kern = ar == Arith::F64 ? "f64" : ar == Arith::F32 ? "f32" : pl.use_x ? "b3x" : "b3";
+  std::snprintf(buf, sizeof(buf), "%s%s m=%lld n=%lld k=%lld tiles=%dx%d splits=%d store=%s", kern,
+                pl.use_x ? (pl.xbn == 192 ? "192" : "256") : "", (long long)pl.M, (long long)pl.N,
+                (long long)pl.K, a.tiles_m, a.tiles_n, a.splits,
+                a.cm == 1 ? "m4" : a.cm == 2 ? "m1" : a.cvec ? "n4" : "n1");
+  return buf;
+}
+
+hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* la_, const void* B,
+                    const char* lb_, void* C, const char* lc_, bool c_f64, double alpha,
+                    double beta, hipStream_t stream, double* flops, double* scratch,
+                    size_t scratch_elems, const LabelDims* cdims) {
+  Plan pl;
+  const hipError_t pe = choose_plan(ar, dims, cdims ? *cdims : dims, A, la_, B, lb_, C, lc_, c_f64,
+                                    alpha, beta, scratch, scratch_elems, pl);
+  if (pe != hipSuccess) return pe;
+  if (flops) *flops += 2.0 * (double)pl.M * (double)pl.N * (double)pl.K;
+  if (pl.M == 0 || pl.N == 0) return hipSuccess;
+  if (pl.K == 0) return hipErrorInvalidValue;  // the kernels assume at least one k-tile
+  const TcArgs& args = pl.args;
   const int blocks = args.per_xcd * 8;
+  const int splits = args.splits;
   const bool c64 = c_f64 || splits > 1;  // partial sums are kept in double
   hipError_t e;
   if (ar == Arith::F64) {
     if (!c_f64) return hipErrorInvalidValue;
-    e = dispatch<double, double>(args, blocks, A_KC, va, B_NC, vb, kal, stream);
+    e = dispatch<double, double>(args, blocks, pl.A_KC, pl.va, pl.B_NC, pl.vb, pl.kal, stream);
   } else if (ar == Arith::F32) {
-    e = c64 ? dispatch<float, double>(args, blocks, A_KC, va, B_NC, vb, kal, stream)
-            : dispatch<float, float>(args, blocks, A_KC, va, B_NC, vb, kal, stream);
-  } else if (use_x) {
-    e = launch_contract_b3x(args, xbn, c64, stream);
+    e = c64 ? dispatch<float, double>(args, blocks, pl.A_KC, pl.va, pl.B_NC, pl.vb, pl.kal, stream)
+            : dispatch<float, float>(args, blocks, pl.A_KC, pl.va, pl.B_NC, pl.vb, pl.kal, stream);
+  } else if (pl.use_x) {
+    e = launch_contract_b3x(args, pl.xbn, c64, stream);
   } else {
-    e = launch_contract_b3(args, A_KC, va, B_NC, vb, kal, c64, stream);
+    e = launch_contract_b3(args, pl.A_KC, pl.va, pl.B_NC, pl.vb, pl.kal, c64, stream);
   }
   if (e != hipSuccess || splits == 1) return e;
-  const int64_t mn = M * N;
+  const int64_t mn = pl.M * pl.N;
   const int grid = (int)std::min<int64_t>((mn + 255) / 256, 8192);
   if (c_f64)
     hipLaunchKernelGGL(tc_splitk_reduce<double>, dim3(grid), dim3(256), 0, stream, args);

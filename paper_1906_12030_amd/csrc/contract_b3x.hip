@@ -84,8 +84,11 @@ constexpr int lds_bytes() {
   return 2 * Geo<BN>::kStage;
 }
 
-// Epilogue: each wave parks one 16-row group of its accumulators in LDS and
-// re-reads it so that every lane stores 16 contiguous bytes.
+// Epilogue: when C is contiguous along n, each wave parks one 16-row group of
+// its accumulators in LDS and re-reads it so that every lane stores 16
+// contiguous bytes along n; when C is contiguous along m (TcArgs::cm), the
+// accumulators already hold four consecutive rows per lane and are stored
+// directly.
 template <typename TC, int BN>
 __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[8][Geo<BN>::kWNB],
                                              uint32_t m0, uint32_t n0, int split, char* lds,
@@ -114,6 +117,51 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[8][Geo
   TC* __restrict__ C = p.splits > 1 ? reinterpret_cast<TC*>(p.part) : static_cast<TC*>(p.c);
   const double alpha = p.splits > 1 ? 1.0 : p.alpha;
   const double beta = p.splits > 1 ? 0.0 : p.beta;
+  if (p.cm != 0 && p.splits == 1) {
+    // C contiguous along m: lane (lr, kq) holds rows 4 kq .. 4 kq + 3 of each
+    // 16 x 16 block, column lr, i.e. four consecutive C elements; a wave's
+    // store covers 16 columns x 16 rows.  No staging needed.
+    __syncthreads();  // offsets staged
+    const bool mvec = p.cm == 1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int r0 = wm + i * 16 + 4 * (lane >> 4);
+      if (rows[r0] < 0) continue;  // rows past M come last
+#pragma unroll
+      for (int j = 0; j < G::kWNB; ++j) {
+        const int64_t co = cols[wn + j * 16 + (lane & 15)];
+        if (co < 0) continue;
+        if (mvec) {  // rows r0 .. r0 + 3 are all inside M (M % 4 == 0) and adjacent in C
+          TC* dst = C + rows[r0] + co;
+          TC out[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            double y = alpha * (double)acc[i][j][e];
+            if (beta != 0.0) y += beta * load_c(p, dst + e);
+            out[e] = store_c<TC>(p, y);
+          }
+          if constexpr (sizeof(TC) == 4) {
+            *reinterpret_cast<f4_t*>(dst) = f4_t{out[0], out[1], out[2], out[3]};
+          } else {
+            typedef double d2_t __attribute__((ext_vector_type(2)));
+            *reinterpret_cast<d2_t*>(dst) = d2_t{out[0], out[1]};
+            *reinterpret_cast<d2_t*>(dst + 2) = d2_t{out[2], out[3]};
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t re = rows[r0 + e];
+            if (re < 0) continue;
+            TC* dst = C + re + co;
+            double y = alpha * (double)acc[i][j][e];
+            if (beta != 0.0) y += beta * load_c(p, dst);
+            *dst = store_c<TC>(p, y);
+          }
+        }
+      }
+    }
+    return;
+  }
   const bool vec = p.cvec != 0;
   constexpr int PER_ROW = G::kWN / 4;       // 16-byte vectors per staged row
   constexpr int ITER = 16 * PER_ROW / 64;   // vectors per lane

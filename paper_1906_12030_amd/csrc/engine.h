@@ -50,6 +50,14 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
 // Flop count of the same contraction without launching anything.
 double contract_flops(const LabelDims& dims, const char* la, const char* lb, const char* lc);
 
+// The kernel contract() would choose for the same labels and sizes, as one
+// line ("b3x192 m=... n=... k=... tiles=MxN splits=S store=m4", store n4/n1 =
+// vector/element stores along n, m4/m1 along m; "unsupported" for label sets
+// contract() rejects).  Host only, assumes 16-byte aligned operands.
+std::string contract_plan(Arith ar, const LabelDims& dims, const char* la, const char* lb,
+                          const char* lc, bool c_f64, size_t scratch_elems,
+                          const LabelDims* cdims = nullptr);
+
 // ---- MFMA throughput microbenchmark (peak.hip) ----
 // kind 0: bf16 16x16x32, 1: f32 16x16x4, 2: f64 16x16x4; `out` holds
 // blocks*256 floats; flops of one launch = blocks*4 waves*iters*per_wave_iter.
@@ -59,6 +67,8 @@ double mfma_peak_flops_per_wave_iter(int kind);
 // ---- auxiliary kernels (aux.hip) ----
 // y[i] = (float) x[i]; with split, y holds split words (hi|lo bf16) of (float) x[i]
 hipError_t launch_to_f32(const double* x, float* y, int64_t n, bool split, hipStream_t s);
+// y = split words of the d^6 density x[i j k I J K], stored as y[j k J K i I]
+hipError_t launch_rho_to_split_perm(const double* x, float* y, int32_t d, hipStream_t s);
 // y[i] = a * x[i]
 hipError_t launch_scale(const double* x, double* y, double a, int64_t n, hipStream_t s);
 // fill y with value

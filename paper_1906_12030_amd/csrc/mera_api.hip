@@ -46,11 +46,20 @@ void set_err(const std::string& s) { g_last_error = s; }
 struct ProfRec {
   std::string step;
   int arith;
+  int op;
   double flops;
   hipEvent_t a, b;
 };
 thread_local bool g_prof_on = false;
 thread_local std::vector<ProfRec> g_prof;
+thread_local int g_prof_op = -1;  // mera_op of the entry point running on this thread
+
+// Tags the contraction launches of one entry point in the profile records.
+struct OpTag {
+  int prev;
+  explicit OpTag(int op) : prev(g_prof_op) { g_prof_op = op; }
+  ~OpTag() { g_prof_op = prev; }
+};
 
 using mera::Arith;
 using mera::LabelDims;
@@ -67,6 +76,7 @@ struct Ctx {
   hipError_t err = hipSuccess;
   double* scratch = nullptr;  // split-k partial sums (see contract())
   size_t scratch_elems = 0;
+  std::vector<std::string>* plans = nullptr;  // dry mode: kernel choice of every contraction
 
   size_t elem() const { return ar == Arith::F64 ? 8 : 4; }
   // reserve `count` elements of `bytes_per` bytes, 256-byte aligned
@@ -84,6 +94,10 @@ struct Ctx {
          bool c_f64, double alpha, double beta, const LabelDims* cdims = nullptr) {
     if (dry) {
       flops += mera::contract_flops(dims, la, lb, lc);
+      if (plans)
+        plans->push_back(std::string(la) + "," + lb + "->" + lc + " " +
+                         mera::contract_plan(ar, dims, la, lb, lc, ar == Arith::F64 || c_f64,
+                                             scratch_elems, cdims));
       return;
     }
     if (err != hipSuccess) return;
@@ -92,6 +106,7 @@ struct Ctx {
     if (g_prof_on) {
       rec.step = std::string(la) + "," + lb + "->" + lc;
       rec.arith = (int)ar;
+      rec.op = g_prof_op;
       rec.flops = mera::contract_flops(dims, la, lb, lc);
       if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) {
         err = hipErrorOutOfMemory;
@@ -151,6 +166,23 @@ const void* working_op(Ctx& cx, const double* x, int64_t n) {
   return xf;
 }
 
+// Layouts for the split-bf16 path (see Pieces and x_copies).
+bool k_contiguous_layouts(const Ctx& cx) { return cx.ar == Arith::B3; }
+
+// A dout^6 density in the working type, with its labels: the split-bf16 path
+// moves the legs of the first fine-grained window pair (i, I) innermost, the
+// legs the first contraction of every chain sums over.
+struct WorkingRho {
+  const void* p;
+  const char* l;
+};
+WorkingRho working_rho(Ctx& cx, const double* rho, int64_t dout) {
+  if (!k_contiguous_layouts(cx)) return {working_op(cx, rho, ipow(dout, 6)), "ijkIJK"};
+  float* y = static_cast<float*>(cx.take(ipow(dout, 6), 4));
+  if (!cx.dry) cx.check(mera::launch_rho_to_split_perm(rho, y, (int32_t)dout, cx.s), "rho_to_split");
+  return {y, "jkJKiI"};
+}
+
 void set_dims(Ctx& cx, int din, int dout) {
   cx.dims = LabelDims();
   cx.dims.set("pqrsPQRSabcdABCDxy", din);
@@ -175,10 +207,10 @@ struct Pieces {
   void* M3;  // [p c q a j]; split bf16: [p a j c q]
   const char* n3;  // labels of N3 as (R B s D J) legs
   const char* m3;  // labels of M3 as (p C Q A J) legs
+  const char* lp;  // labels of Lp: [a i A I]; split bf16: [a A i I]
+  const char* rp;  // labels of Rp: [d k D K]; split bf16: [d D k K]
+  const char* x1;  // labels of X1 = Lp . rho: [a j k A J K]; split bf16: [a j A J k K]
 };
-
-// Layouts for the split-bf16 path (see Pieces and x_copies).
-bool k_contiguous_layouts(const Ctx& cx) { return cx.ar == Arith::B3; }
 
 Pieces build_pieces(Ctx& cx, const LayerT& t, int64_t din, int64_t dout) {
   Pieces pc;
@@ -189,10 +221,13 @@ Pieces build_pieces(Ctx& cx, const LayerT& t, int64_t din, int64_t dout) {
   pc.M = cx.take_t(ipow(din, 4) * dout);
   pc.M1 = cx.take_t(ipow(din, 4) * dout);
   pc.M3 = cx.take_t(ipow(din, 4) * dout);
-  cx.c(t.w, "xai", t.w, "xAI", pc.Lp, "aiAI", false, 1.0, 0.0);
-  cx.c(t.w, "dyk", t.w, "DyK", pc.Rp, "dkDK", false, 1.0, 0.0);
-  cx.c(t.w, "bcj", t.u, "rscd", pc.N, "rsbdj", false, 1.0, 0.0);
   const bool kc = k_contiguous_layouts(cx);
+  pc.lp = kc ? "aAiI" : "aiAI";
+  pc.rp = kc ? "dDkK" : "dkDK";
+  pc.x1 = kc ? "ajAJkK" : "ajkAJK";
+  cx.c(t.w, "xai", t.w, "xAI", pc.Lp, pc.lp, false, 1.0, 0.0);
+  cx.c(t.w, "dyk", t.w, "DyK", pc.Rp, pc.rp, false, 1.0, 0.0);
+  cx.c(t.w, "bcj", t.u, "rscd", pc.N, "rsbdj", false, 1.0, 0.0);
   cx.c(t.w, "bcj", t.u, "rscd", pc.N3, kc ? "sdjrb" : "rbsdj", false, 1.0, 0.0);
   pc.n3 = kc ? "sDJRB" : "RBsDJ";
   pc.m3 = kc ? "pAJCQ" : "pCQAJ";
@@ -203,10 +238,11 @@ Pieces build_pieces(Ctx& cx, const LayerT& t, int64_t din, int64_t dout) {
 }
 
 // X[j a d A D J] = sum Lp[a i A I] rho[i j k I J K] Rp[d k D K]; keeps X1 = Lp.rho.
-// X may be null when only the k-contiguous copies are needed.
-void build_x(Ctx& cx, const Pieces& pc, const void* rho, void* X1, void* X) {
-  cx.c(pc.Lp, "aiAI", rho, "ijkIJK", X1, "ajkAJK", false, 1.0, 0.0);
-  if (X) cx.c(X1, "ajkAJK", pc.Rp, "dkDK", X, "djaADJ", false, 1.0, 0.0);
+// with_x = false skips X when only the k-contiguous copies are needed.  The
+// dout^4-row operand comes first (the m side of the large-tile kernel).
+void build_x(Ctx& cx, const Pieces& pc, const WorkingRho& rho, void* X1, void* X, bool with_x) {
+  cx.c(rho.p, rho.l, pc.Lp, pc.lp, X1, pc.x1, false, 1.0, 0.0);
+  if (with_x) cx.c(X1, pc.x1, pc.Rp, pc.rp, X, "djaADJ", false, 1.0, 0.0);
 }
 
 // Copies of X for the first chi^9 contraction of each chain, with the summed
@@ -225,8 +261,8 @@ XCopies x_copies(Ctx& cx, const Pieces& pc, const void* X1, const void* X, int64
   if (!k_contiguous_layouts(cx)) return {X, X, "djaADJ", "djaADJ"};
   void* xl = cx.take_t(ipow(din, 4) * dout * dout);
   void* xr = cx.take_t(ipow(din, 4) * dout * dout);
-  cx.c(X1, "ajkAJK", pc.Rp, "dkDK", xl, "aADJdj", false, 1.0, 0.0);
-  cx.c(X1, "ajkAJK", pc.Rp, "dkDK", xr, "dDAJja", false, 1.0, 0.0);
+  cx.c(X1, pc.x1, pc.Rp, pc.rp, xl, "aADJdj", false, 1.0, 0.0);
+  cx.c(X1, pc.x1, pc.Rp, pc.rp, xr, "dDAJja", false, 1.0, 0.0);
   return {xl, xr, "aADJdj", "dDAJja"};
 }
 
@@ -256,12 +292,19 @@ int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_
   const int64_t din = L->din, dout = L->dout;
   set_dims(cx, (int)din, (int)dout);
   LayerT t = working_layer(cx, L);
-  const void* rho = working_op(cx, rho_in, ipow(dout, 6));
+  const WorkingRho rho = working_rho(cx, rho_in, dout);
   Pieces pc = build_pieces(cx, t, din, dout);
   void* X1 = cx.take_t(din * din * ipow(dout, 4));
-  void* X = k_contiguous_layouts(cx) ? nullptr : cx.take_t(ipow(din, 4) * dout * dout);
+  const bool kc = k_contiguous_layouts(cx);
+  void* X = kc ? nullptr : cx.take_t(ipow(din, 4) * dout * dout);
+  // chi^6 intermediates of the chains; the split-bf16 path stores each with
+  // the legs the next contraction sums over innermost
+  const char* mid_l = kc ? "rABRab" : "rabABR";
+  const char* mid2_l = kc ? "pqrRAB" : "pqrABR";
+  const char* mid_r = kc ? "qDCQcd" : "qcdDCQ";
+  const char* mid2_r = kc ? "qrsQCD" : "qrsCDQ";
   const int64_t R = (din + slices - 1) / slices;
-  build_x(cx, pc, rho, X1, X);
+  build_x(cx, pc, rho, X1, X, !kc);
   const XCopies xc = x_copies(cx, pc, X1, X, din, dout);
   Bufs b = take_bufs(cx, din, dout, R);
   const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
@@ -274,9 +317,9 @@ int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_
       cx.dims.d['r'] = std::min(R, din - r0);
       const char* n_s = static_cast<const char*>(pc.N) + r0 * ipow(din, 3) * dout * es;  // N[r0, ...]
       cx.c(n_s, "rsbdj", xc.l, xc.xl, b.big, "rsbaADJ", false, 1.0, 0.0);
-      cx.c(b.big, "rsbaADJ", pc.N, "RsBDJ", b.mid, "rabABR", false, 1.0, 0.0);
-      cx.c(b.mid, "rabABR", t.u, "pqab", b.mid2, "pqrABR", false, 1.0, 0.0);
-      cx.c(b.mid2, "pqrABR", t.u, "PQAB", rho_out + r0 * ipow(din, 3), "pqrPQR", true, wgt, 0.0, &full);
+      cx.c(b.big, "rsbaADJ", pc.N, "RsBDJ", b.mid, mid_l, false, 1.0, 0.0);
+      cx.c(b.mid, mid_l, t.u, "pqab", b.mid2, mid2_l, false, 1.0, 0.0);
+      cx.c(b.mid2, mid2_l, t.u, "PQAB", rho_out + r0 * ipow(din, 3), "pqrPQR", true, wgt, 0.0, &full);
     }
     cx.dims = full;
     first = false;
@@ -287,9 +330,9 @@ int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_
       cx.dims.d['q'] = std::min(R, din - q0);
       const char* m_s = static_cast<const char*>(pc.M1) + q0 * ipow(din, 3) * dout * es;  // M1[q0, ...]
       cx.c(m_s, "qpcja", xc.r, xc.xr, b.big, "pqcdDAJ", false, 1.0, 0.0);
-      cx.c(b.big, "pqcdDAJ", pc.M, "pQCAJ", b.mid, "qcdDCQ", false, 1.0, 0.0);
-      cx.c(b.mid, "qcdDCQ", t.u, "rscd", b.mid2, "qrsCDQ", false, 1.0, 0.0);
-      cx.c(b.mid2, "qrsCDQ", t.u, "RSCD", rho_out + q0 * ipow(din, 5), "qrsQRS", true, wgt,
+      cx.c(b.big, "pqcdDAJ", pc.M, "pQCAJ", b.mid, mid_r, false, 1.0, 0.0);
+      cx.c(b.mid, mid_r, t.u, "rscd", b.mid2, mid2_r, false, 1.0, 0.0);
+      cx.c(b.mid2, mid2_r, t.u, "RSCD", rho_out + q0 * ipow(din, 5), "qrsQRS", true, wgt,
            first ? 0.0 : 1.0, &full);
     }
     cx.dims = full;
@@ -340,8 +383,8 @@ int run_ascend(Ctx& cx, const mera_layer* L, const double* h_in, double* h_out, 
     cx.c(b.mid, "qcdDCQ", pc.M3, pc.m3, b.big, "pqcdADJ", false, 1.0, 0.0);
     cx.c(pc.M, "pqcaj", b.big, "pqcdADJ", Xb, "djaADJ", false, 1.0, first ? 0.0 : 1.0);
   }
-  cx.c(Xb, "djaADJ", pc.Rp, "dkDK", Z1, "ajkAJK", false, 1.0, 0.0);
-  cx.c(Z1, "ajkAJK", pc.Lp, "aiAI", h_out, "ijkIJK", true, 1.0, 0.0);
+  cx.c(Xb, "djaADJ", pc.Rp, pc.rp, Z1, "ajkAJK", false, 1.0, 0.0);
+  cx.c(Z1, "ajkAJK", pc.Lp, pc.lp, h_out, "ijkIJK", true, 1.0, 0.0);
   return 0;
 }
 
@@ -356,7 +399,7 @@ int run_env(Ctx& cx, const mera_layer* L, const double* h_in, const double* rho_
   set_dims(cx, (int)din, (int)dout);
   LayerT t = working_layer(cx, L);
   const void* h = working_op(cx, h_in, ipow(din, 6));
-  const void* rho = working_op(cx, rho_in, ipow(dout, 6));
+  const WorkingRho rho = working_rho(cx, rho_in, dout);
   Pieces pc = build_pieces(cx, t, din, dout);
   void* X1 = cx.take_t(din * din * ipow(dout, 4));
   void* X = cx.take_t(ipow(din, 4) * dout * dout);
@@ -368,7 +411,7 @@ int run_env(Ctx& cx, const mera_layer* L, const double* h_in, const double* rho_
   void* dLp = want_u ? nullptr : cx.take_t(din * din * dout * dout);
   void* dRp = want_u ? nullptr : cx.take_t(din * din * dout * dout);
   // env accumulators: written in FP64 directly by the final contractions
-  build_x(cx, pc, rho, X1, X);
+  build_x(cx, pc, rho, X1, X, true);
   const XCopies xc = want_u ? x_copies(cx, pc, X1, X, din, dout) : XCopies{X, X, "djaADJ", "djaADJ"};
   const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
   bool first_env = true;
@@ -417,10 +460,10 @@ int run_env(Ctx& cx, const mera_layer* L, const double* h_in, const double* rho_
   }
   if (!want_u) {
     // isometries inside Lp and Rp (ket copies wL = w[x a i], wR = w[d y k])
-    cx.c(dX, "djaADJ", pc.Rp, "dkDK", V1, "ajkAJK", false, 1.0, 0.0);
-    cx.c(V1, "ajkAJK", rho, "ijkIJK", dLp, "aiAI", false, 1.0, 0.0);
+    cx.c(dX, "djaADJ", pc.Rp, pc.rp, V1, "ajkAJK", false, 1.0, 0.0);
+    cx.c(V1, "ajkAJK", rho.p, rho.l, dLp, "aiAI", false, 1.0, 0.0);
     acc_env(dLp, "aiAI", t.w, "xAI", "xai");
-    cx.c(X1, "ajkAJK", dX, "djaADJ", dRp, "dkDK", false, 1.0, 0.0);
+    cx.c(X1, pc.x1, dX, "djaADJ", dRp, "dkDK", false, 1.0, 0.0);
     acc_env(dRp, "dkDK", t.w, "DyK", "dyk");
   }
   return 0;
@@ -558,6 +601,7 @@ int mera_profile_end(mera_profile_entry* out, int32_t max_entries, int32_t* n_ou
       std::memset(out[n].step, 0, sizeof(out[n].step));
       std::strncpy(out[n].step, r.step.c_str(), sizeof(out[n].step) - 1);
       out[n].arith = r.arith;
+      out[n].op = r.op;
       out[n].flops = r.flops;
       out[n].ms = ms;
       ++n;
@@ -693,6 +737,7 @@ int mera_mfma_peak(int kind, void* scratch_d, size_t scratch_bytes, double* tflo
 
 int mera_descend(const mera_layer* layer, const double* rho_in_d, double* rho_out_d, int placement,
                  int precision, void* ws_d, size_t ws_bytes, void* hip_stream) {
+  OpTag tag(MERA_OP_DESCEND);
   int st = check_layer(layer);
   if (st) return st;
   if ((st = check_enum(placement, precision))) return st;
@@ -715,6 +760,7 @@ int mera_descend(const mera_layer* layer, const double* rho_in_d, double* rho_ou
 
 int mera_ascend(const mera_layer* layer, const double* h_in_d, double* h_out_d, int placement,
                 int precision, void* ws_d, size_t ws_bytes, void* hip_stream) {
+  OpTag tag(MERA_OP_ASCEND);
   int st = check_layer(layer);
   if (st) return st;
   if ((st = check_enum(placement, precision))) return st;
@@ -730,6 +776,7 @@ int mera_ascend(const mera_layer* layer, const double* h_in_d, double* h_out_d, 
 
 int mera_env_u(const mera_layer* layer, const double* h_d, const double* rho_d, double* env_u_d,
                int placement, int precision, void* ws_d, size_t ws_bytes, void* hip_stream) {
+  OpTag tag(MERA_OP_ENV_U);
   int st = check_layer(layer);
   if (st) return st;
   if ((st = check_enum(placement, precision))) return st;
@@ -746,6 +793,7 @@ int mera_env_u(const mera_layer* layer, const double* h_d, const double* rho_d, 
 
 int mera_env_w(const mera_layer* layer, const double* h_d, const double* rho_d, double* env_w_d,
                int placement, int precision, void* ws_d, size_t ws_bytes, void* hip_stream) {
+  OpTag tag(MERA_OP_ENV_W);
   int st = check_layer(layer);
   if (st) return st;
   if ((st = check_enum(placement, precision))) return st;
@@ -862,6 +910,7 @@ int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* o
 
 int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int precision,
                          double* resid_d, void* ws_d, size_t ws_bytes, void* hip_stream) {
+  OpTag tag(MERA_OP_FIXED_POINT);
   int st = check_layer(si);
   if (st) return st;
   if ((st = check_enum(MERA_AVG, precision))) return st;
@@ -1104,6 +1153,47 @@ size_t mera_workspace_bytes_min(int op, int32_t din, int32_t dout, int precision
     run_descend(cx, &L, dummy, out, MERA_AVG, din);
   }
   return std::max(hi, cx.off);
+}
+
+int mera_schedule_plan(int op, int32_t din, int32_t dout, int precision, int placement, char* out,
+                       size_t out_bytes, size_t* needed) {
+  if (precision < MERA_FP64 || precision > MERA_BF16X3 || placement < MERA_LEFT ||
+      placement > MERA_AVG) {
+    set_err("mera_schedule_plan: enum out of range");
+    return MERA_EINVAL;
+  }
+  if (din < 1 || dout < 1 || (int64_t)dout > (int64_t)din * din ||
+      (op == MERA_OP_FIXED_POINT && din != dout)) {
+    set_err("mera_schedule_plan: bad dimensions");
+    return MERA_ESHAPE;
+  }
+  mera_layer L{din, dout, reinterpret_cast<const double*>(256), reinterpret_cast<const double*>(256)};
+  const double* dummy = reinterpret_cast<const double*>(256);
+  double* o = reinterpret_cast<double*>(256);
+  std::vector<std::string> plans;
+  Ctx cx;
+  cx.dry = true;
+  cx.ar = arith_of(precision);
+  cx.plans = &plans;
+  switch (op) {
+    case MERA_OP_ASCEND: run_ascend(cx, &L, dummy, o, placement); break;
+    case MERA_OP_DESCEND: run_descend(cx, &L, dummy, o, placement); break;
+    case MERA_OP_ENV_U: run_env(cx, &L, dummy, dummy, o, placement, true); break;
+    case MERA_OP_ENV_W: run_env(cx, &L, dummy, dummy, o, placement, false); break;
+    case MERA_OP_FIXED_POINT: run_descend(cx, &L, dummy, o, MERA_AVG); break;
+    default:
+      set_err("mera_schedule_plan: op has no contractions");
+      return MERA_EINVAL;
+  }
+  std::string text;
+  for (const auto& ln : plans) text += ln + "\n";
+  if (needed) *needed = text.size() + 1;
+  if (out && out_bytes > 0) {
+    const size_t n = std::min(out_bytes - 1, text.size());
+    std::memcpy(out, text.data(), n);
+    out[n] = 0;
+  }
+  return MERA_OK;
 }
 
 double mera_flops(int op, int32_t din, int32_t dout, int placement) {

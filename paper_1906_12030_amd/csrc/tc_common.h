@@ -33,6 +33,11 @@ struct TcArgs {
   int32_t splits, kchunk;  // k range of split s: [s*kchunk, min(K, (s+1)*kchunk))
   int32_t cvec;            // 64-wide output column spans are contiguous (vector stores)
   int32_t csplit;          // FP32 C is stored as split words (see pack_split)
+  // Large-tile kernel only: 0 = C's innermost leg is an n leg (stores along
+  // n); 1 = it is the innermost m leg, with unit stride, a multiple of 4 long
+  // and every other C stride a multiple of 4 (four consecutive rows form one
+  // aligned vector); 2 = it is an m leg otherwise (element stores along m).
+  int32_t cm;
 };
 
 // Split word: a 4-byte element holding x as two bf16 halves, hi = bf16_rne(x)

@@ -157,3 +157,60 @@ def test_contract_argument_checks(lib):
     assert call("ab", "cd", "ac", "abcd", [2, 3, 4, 5]) == _lib.MERA_ESHAPE  # b, d summed in one operand
     assert call("ab", "bc", "ax", "abc", [2, 3, 4]) == _lib.MERA_ESHAPE      # unknown label
     assert call("ab", "bc", "ac", "abc", [1 << 31, 3, 4]) == _lib.MERA_ESHAPE
+
+
+def _plans(op, d_in, d_out, prec, placement=_lib.MERA_AVG):
+    st, lines = _lib.mera_schedule_plan(op, d_in, d_out, prec, placement)
+    assert st == _lib.MERA_OK
+    out = []
+    for ln in lines:
+        labels, kern, *rest = ln.split()
+        kv = dict(x.split("=") for x in rest)
+        out.append((labels, kern, int(kv["m"]), int(kv["n"]), int(kv["k"]), kv["store"]))
+    return out
+
+
+def test_schedule_plan_split_bf16_descend_on_large_tile_kernel(lib):
+    """Every chi^8 and chi^9 contraction of the split-bf16 descend (the fixed-point
+    iteration) is planned on the large-tile kernel, with a column tile that divides
+    chi^2 = 576 where that operand is the n side; the intermediates whose innermost
+    leg is an m leg are stored along m."""
+    chi = 24
+    plans = _plans(_lib.MERA_OP_DESCEND, chi, chi, _lib.MERA_BF16X3)
+    big = [p for p in plans if p[2] * p[3] * p[4] >= chi ** 8]
+    assert len(big) == 11  # X1, two copies of X, four chi^9 and four chi^8 chain steps
+    for labels, kern, m, n, k, store in big:
+        assert kern.startswith("b3x"), (labels, kern)
+        if n == chi * chi:
+            assert kern == "b3x192", labels
+        assert store in ("n4", "m4"), (labels, store)
+    assert sum(p[5] == "m4" for p in big) >= 6
+    # flops: the FP64 schedule is the one mera_flops counts; the split-bf16 one
+    # forms two k-contiguous copies of X (one chi^8 contraction more)
+    p64 = _plans(_lib.MERA_OP_DESCEND, chi, chi, _lib.MERA_FP64)
+    f64 = sum(2.0 * m * n * k for _, _, m, n, k, _ in p64)
+    assert f64 == _lib.load().mera_flops(_lib.MERA_OP_DESCEND, chi, chi, _lib.MERA_AVG)
+    fb3 = sum(2.0 * m * n * k for _, _, m, n, k, _ in plans)
+    assert fb3 == f64 + 2.0 * chi ** 8
+    # the same steps in FP64 and FP32 keep their own kernels
+    assert {p[1] for p in p64} == {"f64"}
+    assert {p[1] for p in _plans(_lib.MERA_OP_DESCEND, chi, chi, _lib.MERA_FP32)} == {"f32"}
+
+
+def test_schedule_plan_argument_checks(lib):
+    st, _ = _lib.mera_schedule_plan(_lib.MERA_OP_DESCEND, 8, 8, 5, _lib.MERA_AVG)
+    assert st == _lib.MERA_EINVAL
+    st, _ = _lib.mera_schedule_plan(_lib.MERA_OP_DESCEND, 8, 8, 0, 9)
+    assert st == _lib.MERA_EINVAL
+    st, _ = _lib.mera_schedule_plan(_lib.MERA_OP_FIXED_POINT, 8, 4, 0, _lib.MERA_AVG)
+    assert st == _lib.MERA_ESHAPE
+    st, _ = _lib.mera_schedule_plan(_lib.MERA_OP_DESCEND, 2, 5, 0, _lib.MERA_AVG)
+    assert st == _lib.MERA_ESHAPE
+    st, _ = _lib.mera_schedule_plan(_lib.MERA_OP_POLAR, 8, 8, 0, _lib.MERA_AVG)
+    assert st == _lib.MERA_EINVAL
+    # truncation: a short buffer holds a NUL-terminated prefix, *needed the full size
+    lib_ = _lib.load()
+    need = ctypes.c_size_t(0)
+    buf = ctypes.create_string_buffer(16)
+    assert lib_.mera_schedule_plan(_lib.MERA_OP_ASCEND, 4, 4, 0, 2, buf, 16, ctypes.byref(need)) == 0
+    assert len(buf.value) == 15 and need.value > 16
