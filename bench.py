@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 # HBM traffic per chi^9 split-bf16 launch at chi=24, from the FETCH_SIZE / WRITE_SIZE
 # counter runs summarised in profiles/b3_contraction_traffic_chi24.md (copy-calibrated).
 # Valid only for the kernel sources it was measured on (hash of csrc/*).
-TRAFFIC_RECORD = {"source_hash": "5e21c54165108b4c", "bytes_per_launch": 33.49e9}
+TRAFFIC_RECORD = {"source_hash": "699bdbabf0aa9881", "bytes_per_launch": 33.58e9}
 
 
 def kernel_source_hash() -> str:
@@ -179,9 +179,7 @@ def traffic_probe(args):
     chi = args.chi
     u, w = inputs.random_layer(np.random.default_rng(args.seed), chi, chi)
     lay = ops.Layer(torch.from_numpy(u).cuda(), torch.from_numpy(w).cuda())
-    n = chi ** 3
-    g = torch.randn(n, 64, dtype=torch.float64, device="cuda")
-    rho = (g @ g.t()).div_(n).reshape((chi,) * 6).contiguous()
+    rho = torch.from_numpy(inputs.random_density(np.random.default_rng(args.seed + 1), chi)).cuda()
     out = ops.descend(lay, rho, "avg", args.precision)
     torch.cuda.synchronize()
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void tc_mfma_kernel(TcArgs p) {
   // k-tile fetch: carry walk for k-aligned tiles, leg decomposition otherwise
   auto fetch = [&](int kt) {
     if constexpr (KAL) {
-      if (kt > 0) kw.next(p.gk);
+      if (kt > 0) kw.next();
       la.load_at(A, kw.oa);
       lb.load_at(B, kw.ob);
     } else {

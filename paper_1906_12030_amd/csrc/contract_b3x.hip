@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
   KWalk<kBK> kw;
   kw.init(p.gk, kbeg);
   auto issue = [&](int stage, int kt) {
-    if (kt > 0) kw.next(p.gk);
+    if (kt > 0) kw.next();
     char* sa = smem + stage * G::kStage;
     char* sb = sa + G::kATile;
     const int64_t ka = 4 * kw.oa, kb = 4 * kw.ob;

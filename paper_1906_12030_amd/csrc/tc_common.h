@@ -211,44 +211,57 @@ struct TileLoad {
 
 // Uniform walk over k-tiles of a k group whose innermost leg's extent is a
 // multiple of the tile: keeps the leg digits of the tile start and its offsets
-// in both operands, advancing by carries instead of divisions.  Digits are
-// held innermost first (dig[0] = innermost leg), so a step is one add and one
-// compare unless the innermost leg wraps.
+// in both operands, advancing by carries instead of divisions.  The group is
+// copied at init, innermost leg first, into registers indexed only by
+// compile-time constants, so a step issues no memory loads; it is one add and
+// one compare unless the innermost leg wraps.
 template <int BK>
 struct KWalk {
-  int32_t dig[kMaxDims];
+  int32_t dig[kMaxDims];       // digits, innermost leg first
+  int32_t sz[kMaxDims];        // extents, innermost first
+  int64_t ca[kMaxDims], cb[kMaxDims];  // offset change when leg j wraps into leg j+1
+  int64_t sa, sb;              // offset change of one k-tile step
+  int32_t nd;
   int64_t oa, ob;
   __device__ __forceinline__ void init(const Group& g, uint32_t k0) {
+    nd = g.nd;
     oa = 0;
     ob = 0;
 #pragma unroll
     for (int j = 0; j < kMaxDims; ++j) {
       dig[j] = 0;
+      sz[j] = 1;
+      ca[j] = 0;
+      cb[j] = 0;
       if (j < g.nd) {
         const int d = g.nd - 1 - j;
-        const uint32_t sz = (uint32_t)g.size[d];
-        const uint32_t q = k0 / sz;
-        dig[j] = (int32_t)(k0 - q * sz);
+        sz[j] = g.size[d];
+        const uint32_t q = k0 / (uint32_t)sz[j];
+        dig[j] = (int32_t)(k0 - q * (uint32_t)sz[j]);
         oa += (int64_t)dig[j] * g.sx[d];
         ob += (int64_t)dig[j] * g.sy[d];
         k0 = q;
+        if (d > 0) {
+          ca[j] = g.sx[d - 1] - (int64_t)g.size[d] * g.sx[d];
+          cb[j] = g.sy[d - 1] - (int64_t)g.size[d] * g.sy[d];
+        }
       }
     }
+    sa = (int64_t)BK * g.sx[g.nd - 1];
+    sb = (int64_t)BK * g.sy[g.nd - 1];
   }
-  __device__ __forceinline__ void next(const Group& g) {
-    const int in = g.nd - 1;
+  __device__ __forceinline__ void next() {
     dig[0] += BK;
-    oa += (int64_t)BK * g.sx[in];
-    ob += (int64_t)BK * g.sy[in];
-    // carries toward the outer legs (rare: once per size[in] / BK steps)
+    oa += sa;
+    ob += sb;
+    // carries toward the outer legs (rare: once per extent / BK steps)
 #pragma unroll
     for (int j = 0; j < kMaxDims - 1; ++j) {
-      const int d = in - j;
-      if (j >= in || dig[j] < g.size[d]) break;
-      dig[j] -= g.size[d];
+      if (j + 1 >= nd || dig[j] < sz[j]) break;
+      dig[j] -= sz[j];
       dig[j + 1] += 1;
-      oa += g.sx[d - 1] - (int64_t)g.size[d] * g.sx[d];
-      ob += g.sy[d - 1] - (int64_t)g.size[d] * g.sy[d];
+      oa += ca[j];
+      ob += cb[j];
     }
   }
 };
