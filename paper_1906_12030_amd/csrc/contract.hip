@@ -392,7 +392,7 @@ hipError_t make_plan(Arith ar, const LabelDims& dims, const LabelDims& cd, const
   // Split-bf16 contractions whose operands are both contiguous along k go to
   // the large-tile kernel with direct-to-LDS loads (contract_b3x.hip).
   pl.use_x = ar == Arith::B3 && pl.kal && akc && pl.va && bkc && !bnc && pl.vb &&
-             contract_b3x_fits(M, N, pl.xbn);
+             contract_b3x_fits(M, N, K, pl.xbn);
   if (m_store && !pl.use_x) return hipSuccess;  // the caller plans the swapped order
   const int64_t tbm = pl.use_x ? 256 : kBM, tbn = pl.use_x ? pl.xbn : kBN;
   args.tiles_m = (int32_t)((M + tbm - 1) / tbm);
@@ -498,7 +498,7 @@ std::string contract_plan(Arith ar, const LabelDims& dims, const char* la, const
   const TcArgs& a = pl.args;
   const char* kern = ar == Arith::F64 ? "f64" : ar == Arith::F32 ? "f32" : pl.use_x ? "b3x" : "b3";
   std::snprintf(buf, sizeof(buf), "%s%s m=%lld n=%lld k=%lld tiles=%dx%d splits=%d store=%s", kern,
-                pl.use_x ? (pl.xbn == 192 ? "192" : "256") : "", (long long)pl.M, (long long)pl.N,
+                pl.use_x ? std::to_string(pl.xbn).c_str() : "", (long long)pl.M, (long long)pl.N,
                 (long long)pl.K, a.tiles_m, a.tiles_n, a.splits,
                 a.cm == 1 ? "m4" : a.cm == 2 ? "m1" : a.cvec ? "n4" : "n1");
   return buf;

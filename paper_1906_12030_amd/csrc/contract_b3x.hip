@@ -4,10 +4,13 @@
 // Same arithmetic as contract_b3.hip (split words hi|lo, three BF16 MFMA
 // products per multiply-add, FP32 accumulation), organised for the long
 // chi^9 contractions whose k-tiles both operands store contiguously:
-//   * 256 x BN output tile (BN = 256 or 192), 512 threads = 8 waves in a
-//     2 (m) x 4 (n) grid, each wave 128 x BN/4 on v_mfma_f32_16x16x32_bf16;
-//     twice the tile edge of the 128 x 128 kernel halves the bytes that
-//     have to come through L2 per flop;
+//   * 256 x BN output tile, 512 threads = 8 waves on v_mfma_f32_16x16x32_bf16:
+//     BN = 192 or 256 in a 2 (m) x 4 (n) wave grid (each wave 128 x BN/4,
+//     its B fragments held for the k-tile and its A fragments streamed
+//     through a ring of three), BN = 288 in a 4 x 2 grid (each wave 64 x 144,
+//     A fragments held, B fragments streamed; 21 % fewer LDS bytes per flop
+//     than 256 x 192); twice the tile edge of the 128 x 128 kernel halves the
+//     bytes that have to come through L2 per flop;
 //   * operand k-tiles (32 split words per row) go straight from global
 //     memory into LDS with global_load_lds_dwordx4, in a two-stage ring
 //     with one barrier per k-tile: the loads of tile kt+1 fly while the
@@ -68,14 +71,19 @@ __device__ __forceinline__ void wait_vmcnt() {
 
 template <int BN>
 struct Geo {
-  static constexpr int kWNB = BN / 64;  // 16-column blocks of a wave (4 waves along n)
-  static constexpr int kWN = BN / 4;    // columns of a wave
+  static constexpr int kWGN = BN > 256 ? 2 : 4;  // waves along n
+  static constexpr int kWGM = 8 / kWGN;          // waves along m
+  static constexpr int kWM = kBM / kWGM;         // rows of a wave
+  static constexpr int kWMB = kWM / 16;          // 16-row blocks of a wave
+  static constexpr int kWN = BN / kWGN;          // columns of a wave
+  static constexpr int kWNB = kWN / 16;          // 16-column blocks of a wave
   static constexpr int kATile = kBM * kRowBytes;
   static constexpr int kBTile = BN * kRowBytes;
   static constexpr int kStage = kATile + kBTile;
-  static constexpr int kAIns = kBM / 64;  // 1 KB (8-row) DMA chunks per wave for A
-  static constexpr int kBIns = BN / 64;   // and for B
-  static_assert(BN % 64 == 0 && BN <= 256, "tile width");
+  static constexpr int kAChunks = kBM / 8, kBChunks = BN / 8;  // 1 KB (8-row) DMA chunks
+  static constexpr int kAIns = (kAChunks + 7) / 8;  // per wave
+  static constexpr int kBIns = (kBChunks + 7) / 8;
+  static_assert(kWN % 16 == 0 && BN % 8 == 0, "tile width");
 };
 
 // LDS bytes of the kernel: two stages, reused by the epilogue.
@@ -90,7 +98,7 @@ constexpr int lds_bytes() {
 // accumulators already hold four consecutive rows per lane and are stored
 // directly.
 template <typename TC, int BN>
-__device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[8][Geo<BN>::kWNB],
+__device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[Geo<BN>::kWMB][Geo<BN>::kWNB],
                                              uint32_t m0, uint32_t n0, int split, char* lds,
                                              int wm, int wn) {
   using G = Geo<BN>;
@@ -124,7 +132,7 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[8][Geo
     __syncthreads();  // offsets staged
     const bool mvec = p.cm == 1;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < G::kWMB; ++i) {
       const int r0 = wm + i * 16 + 4 * (lane >> 4);
       if (rows[r0] < 0) continue;  // rows past M come last
 #pragma unroll
@@ -167,7 +175,7 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[8][Geo
   constexpr int ITER = 16 * PER_ROW / 64;   // vectors per lane
   static_assert(16 * PER_ROW % 64 == 0, "epilogue geometry");
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < G::kWMB; ++i) {
     __syncthreads();  // offsets staged / previous row group consumed
 #pragma unroll
     for (int j = 0; j < G::kWNB; ++j)
@@ -224,8 +232,8 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = (wave >> 2) * 128;
-  const int wn = (wave & 3) * G::kWN;
+  const int wm = (wave / G::kWGN) * G::kWM;
+  const int wn = (wave % G::kWGN) * G::kWN;
   const uint32_t m0 = (uint32_t)tm * kBM;
   const uint32_t n0 = (uint32_t)tn * BN;
   const uint32_t kbeg = (uint32_t)split * (uint32_t)p.kchunk;
@@ -251,7 +259,7 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
     for (int q = 0; q < G::kBIns; ++q) {
       const int r = (q * 8 + wave) * 8 + rl;
       const uint32_t rr = n0 + r;
-      const int64_t ro = rr < (uint32_t)p.N ? goff<false>(p.gn, rr) : 0;
+      const int64_t ro = (r < BN && rr < (uint32_t)p.N) ? goff<false>(p.gn, rr) : 0;
       bsrc[q] = 4 * (ro + 4 * (ph ^ swz(r)));
     }
   }
@@ -268,13 +276,14 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
                                        sa + (q * 8 + wave) * 1024, 16, 0, 0);
 #pragma unroll
     for (int q = 0; q < G::kBIns; ++q)
-      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(B + bsrc[q] + kb),
-                                       sb + (q * 8 + wave) * 1024, 16, 0, 0);
+      if (G::kBChunks % 8 == 0 || q * 8 + wave < G::kBChunks)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(B + bsrc[q] + kb),
+                                         sb + (q * 8 + wave) * 1024, 16, 0, 0);
   };
 
-  f4_t acc[8][G::kWNB];
+  f4_t acc[G::kWMB][G::kWNB];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < G::kWMB; ++i)
 #pragma unroll
     for (int j = 0; j < G::kWNB; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
@@ -301,6 +310,7 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
     if (kt + 1 < nk) issue((kt + 1) & 1, kt + 1);
     const char* sa = smem + (kt & 1) * G::kStage;
     const char* sb = sa + G::kATile;
+    if constexpr (G::kWMB == 8) {
     bf8_t bh[G::kWNB], bl[G::kWNB];
 #pragma unroll
     for (int j = 0; j < G::kWNB; ++j) {
@@ -332,6 +342,39 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
       for (int j = 0; j < G::kWNB; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
     }
+      } else {
+      // 4 x 2 wave grid: all A fragments of the wave in registers, B
+      // fragments through a ring of three
+      bf8_t ah[G::kWMB], al[G::kWMB];
+#pragma unroll
+      for (int i = 0; i < G::kWMB; ++i) {
+        const u4_t w0 = *reinterpret_cast<const u4_t*>(sa + abase + i * 16 * kRowBytes + x0);
+        const u4_t w1 = *reinterpret_cast<const u4_t*>(sa + abase + i * 16 * kRowBytes + x1);
+        split8(w0, w1, ah[i], al[i]);
+      }
+      u4_t rb[3][2];
+      auto read_b = [&](int j, u4_t (&r)[2]) {
+        r[0] = *reinterpret_cast<const u4_t*>(sb + bbase + j * 16 * kRowBytes + x0);
+        r[1] = *reinterpret_cast<const u4_t*>(sb + bbase + j * 16 * kRowBytes + x1);
+      };
+      read_b(0, rb[0]);
+      read_b(1, rb[1]);
+#pragma unroll
+      for (int j = 0; j < G::kWNB; ++j) {
+        if (j + 2 < G::kWNB) read_b(j + 2, rb[(j + 2) % 3]);
+        bf8_t bh, bl;
+        split8(rb[j % 3][0], rb[j % 3][1], bh, bl);
+#pragma unroll
+        for (int i = 0; i < G::kWMB; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < G::kWMB; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < G::kWMB; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+      }
+    }
   }
   barrier_nofence();  // the epilogue reuses the stages
 
@@ -340,12 +383,17 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
 
 }  // namespace b3x
 
-bool contract_b3x_fits(int64_t M, int64_t N, int& bn) {
+bool contract_b3x_fits(int64_t M, int64_t N, int64_t K, int& bn) {
   // 256-row tiles; the column tile that wastes the least of N (ties: 256)
   if (M < 256 || N < 192) return false;
+  const int64_t w288 = (N + 287) / 288 * 288 - N;
   const int64_t w256 = (N + 255) / 256 * 256 - N;
   const int64_t w192 = (N + 191) / 192 * 192 - N;
   bn = w192 < w256 ? 192 : 256;
+  // 256 x 288 (4 x 2 waves of 64 x 144) reads 21 % fewer LDS bytes per flop than
+  // 256 x 192 and is faster for long k ranges; for short ones (a few k-tiles
+  // per output tile) its larger epilogue costs more than it saves
+  if (K >= 2048 && w288 <= (bn == 192 ? w192 : w256)) bn = 288;
   return true;
 }
 
@@ -356,6 +404,11 @@ hipError_t launch_contract_b3x(const TcArgs& a, int bn, bool c_f64, hipStream_t 
       hipLaunchKernelGGL((b3x::tc_b3x_kernel<double, 256>), dim3(blocks), dim3(b3x::kThreadsX), 0, s, a);
     else
       hipLaunchKernelGGL((b3x::tc_b3x_kernel<float, 256>), dim3(blocks), dim3(b3x::kThreadsX), 0, s, a);
+  } else if (bn == 288) {
+    if (c_f64)
+      hipLaunchKernelGGL((b3x::tc_b3x_kernel<double, 288>), dim3(blocks), dim3(b3x::kThreadsX), 0, s, a);
+    else
+      hipLaunchKernelGGL((b3x::tc_b3x_kernel<float, 288>), dim3(blocks), dim3(b3x::kThreadsX), 0, s, a);
   } else if (bn == 192) {
     if (c_f64)
       hipLaunchKernelGGL((b3x::tc_b3x_kernel<double, 192>), dim3(blocks), dim3(b3x::kThreadsX), 0, s, a);

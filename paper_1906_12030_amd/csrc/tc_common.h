@@ -98,7 +98,7 @@ hipError_t launch_contract_b3(const TcArgs& a, bool akc, bool va, bool bnc, bool
                               bool c_f64, hipStream_t s);
 // Large-tile split-bf16 kernel (both operands contiguous along k, k-aligned):
 // whether an M x N output suits it (and its column tile), and the launch.
-bool contract_b3x_fits(int64_t M, int64_t N, int& bn);
+bool contract_b3x_fits(int64_t M, int64_t N, int64_t K, int& bn);
 hipError_t launch_contract_b3x(const TcArgs& a, int bn, bool c_f64, hipStream_t s);
 
 }  // namespace mera
