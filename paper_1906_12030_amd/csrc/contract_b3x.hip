@@ -102,13 +102,14 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[Geo<BN
                                              uint32_t m0, uint32_t n0, int split, char* lds,
                                              int wm, int wn) {
   using G = Geo<BN>;
-  constexpr int LD = G::kWN + 4;  // floats per staged row (pad keeps 16-byte alignment)
+  constexpr int LD = BN + 4;  // floats per staged row (pad keeps 16-byte alignment)
   int64_t* rows = reinterpret_cast<int64_t*>(lds);
   int64_t* cols = rows + kBM;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  float* st = reinterpret_cast<float*>(lds + (kBM + BN) * 8) + wave * 16 * LD;
+  // one 16-row x BN staging block per row of waves (the waves sharing wm)
+  float* st = reinterpret_cast<float*>(lds + (kBM + BN) * 8) + (wave / G::kWGN) * 16 * LD;
   for (int i = tid; i < kBM + BN; i += kThreadsX) {
     if (i < kBM) {
       const uint32_t m = m0 + i;
@@ -171,26 +172,32 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[Geo<BN
     return;
   }
   const bool vec = p.cvec != 0;
-  constexpr int PER_ROW = G::kWN / 4;       // 16-byte vectors per staged row
-  constexpr int ITER = 16 * PER_ROW / 64;   // vectors per lane
-  static_assert(16 * PER_ROW % 64 == 0, "epilogue geometry");
+  // The waves of a row of waves park their 16 x kWN blocks side by side, then
+  // each writes 16 / kWGN whole rows of the tile (BN contiguous columns): a
+  // store instruction covers up to 1 KB of one output row.
+  constexpr int PER_ROW = BN / 4;                 // 16-byte vectors per tile row
+  constexpr int ROWS = 16 / G::kWGN;              // rows written by each wave
+  constexpr int ITER = ROWS * PER_ROW / 64;       // vectors per lane
+  static_assert(ROWS * PER_ROW % 64 == 0, "epilogue geometry");
+  const int wr = (wave % G::kWGN) * ROWS;         // this wave's first row in the group
 #pragma unroll
   for (int i = 0; i < G::kWMB; ++i) {
     __syncthreads();  // offsets staged / previous row group consumed
 #pragma unroll
     for (int j = 0; j < G::kWNB; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) st[(4 * (lane >> 4) + r) * LD + j * 16 + (lane & 15)] = acc[i][j][r];
+      for (int r = 0; r < 4; ++r)
+        st[(4 * (lane >> 4) + r) * LD + wn + j * 16 + (lane & 15)] = acc[i][j][r];
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
       const int idx = it * 64 + lane;
-      const int row = idx / PER_ROW;
+      const int row = wr + idx / PER_ROW;
       const int col = (idx % PER_ROW) * 4;
       const int64_t ro = rows[wm + i * 16 + row];
       if (ro < 0) continue;
       const f4_t x = *reinterpret_cast<const f4_t*>(&st[row * LD + col]);
-      const int64_t co = cols[wn + col];
+      const int64_t co = cols[col];
       if (vec && co >= 0) {
         TC* dst = C + ro + co;
         TC out[4];
@@ -210,7 +217,7 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[Geo<BN
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int64_t ce = cols[wn + col + e];
+          const int64_t ce = cols[col + e];
           if (ce < 0) continue;
           TC* dst = C + ro + ce;
           double y = alpha * (double)x[e];
