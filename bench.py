@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--fp32-steps", type=int, default=1,
+                    help="sweeps timed with FP32-MFMA contractions (the other reduced-precision form)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--profile-only", action="store_true",
@@ -283,6 +285,22 @@ def main():
         print(f"# fp64 sweep: {t_fp64:.3f} s/sweep, e = {e_fp64:.12f}", file=sys.stderr, flush=True)
         del m64
 
+    # ---- the FP32-contraction form of the sweep from the same state (time and energy) ----
+    t_fp32 = None
+    e_fp32 = None
+    if args.fp32_steps > 0 and prec != "fp32":
+        m32 = sweep.GpuMera(start_state["layers"], start_state["si"], start_state["rho_star"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.fp32_steps):
+            e, c = sweep.sweep(m32, h1, shift, args.iters, "fp32")
+            if k == 0:
+                e_fp32 = float(e.item()) + shift
+        torch.cuda.synchronize()
+        t_fp32 = (time.perf_counter() - t0) / args.fp32_steps
+        print(f"# fp32 sweep: {t_fp32:.3f} s/sweep, e = {e_fp32:.12f}", file=sys.stderr, flush=True)
+        del m32
+
     # ---- energy evaluation at the final tensors: mixed pipeline vs FP64 pipeline ----
     def eval_energy(precision):
         mm = sweep.GpuMera([(u.clone(), w.clone()) for u, w in m.layers], (m.si[0].clone(), m.si[1].clone()),
@@ -337,6 +355,9 @@ def main():
         "sweep_s_mixed": round(t_mixed, 4),
         "sweep_s_fp64": round(t_fp64, 4) if t_fp64 else None,
         "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3) if t_fp64 else None,
+        "sweep_s_fp32_contractions": round(t_fp32, 4) if t_fp32 else None,
+        "speedup_fp32_vs_fp64": round(t_fp64 / t_fp32, 3) if (t_fp32 and t_fp64) else None,
+        "dE_one_sweep_fp32_vs_fp64": abs(e_fp32 - e_fp64) if (e_fp32 is not None and e_fp64 is not None) else None,
         "sweep_flops": flops,
         "sweep_phase_s": {k: round(v / args.steps, 4) for k, v in phases.items()},
         "contraction_tflops_all_launches": round(all_f / (all_ms / 1e3) / 1e12, 3),

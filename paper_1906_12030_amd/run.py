@@ -2,7 +2,7 @@
 
     python -m paper_1906_12030_amd.run --chi 8 --layers 3 --sweeps 500 --precision fp64 \
         [--seed 0] [--iters 30] [--save state.npz] [--resume state.npz] [--grow-from small.npz]
-        [--dims 12] [--log run.jsonl]
+        [--dims 12] [--log run.jsonl] [--compare-precisions fp64,fp32,bf16x3]
 
 Prints one JSON line per reporting interval (energy per site, error against
 the exact -4/pi of Sec. III.A, seconds per sweep) and, with --dims k, the k
@@ -10,7 +10,10 @@ lowest scaling dimensions of the final scale-invariant layer (Sec. III.A).
 Checkpoints hold every tensor, rho*, the sweep index and the settings; a
 resumed run continues the same trajectory.  --grow-from pads a converged
 smaller-chi state to --chi (zero padding of every leg, seeded N(0, 1e-3)
-noise, re-projection onto isometries) as a warm start.
+noise, re-projection onto isometries) as a warm start.  --compare-precisions
+recomputes rho*, the energy and (with --dims) the scaling dimensions of the final
+tensors with each listed contraction precision and reports the differences from
+the first.
 """
 from __future__ import annotations
 
@@ -96,6 +99,9 @@ def main(argv=None):
     ap.add_argument("--grow-from", default=None)
     ap.add_argument("--dims", type=int, default=0)
     ap.add_argument("--log", default=None)
+    ap.add_argument("--compare-precisions", default=None,
+                    help="comma list, e.g. fp64,fp32,bf16x3: at the final state, rho* (30 warm-started "
+                         "iterations), energy and (with --dims) scaling dimensions in each precision")
     a = ap.parse_args(argv)
     if not torch.cuda.is_available():
         raise SystemExit("a GPU is required")
@@ -132,10 +138,42 @@ def main(argv=None):
     if a.save:
         save_state(a.save, m, {"sweep": start + a.sweeps, "chi": a.chi, "layers": a.layers,
                                "seed": a.seed, "iters": a.iters, "precision": a.precision})
-    if a.dims > 0:
+    if a.dims > 0 and not a.compare_precisions:
         d, lam, calls = scaling.scaling_dimensions(m.si[0], m.si[1], k=a.dims)
         print(json.dumps({"scaling_dimensions": [round(float(x), 6) for x in d], "matvecs": calls}), flush=True)
+    if a.compare_precisions:
+        compare_precisions(m, h1, shift, a.compare_precisions.split(","), a.iters, a.dims)
     return e
+
+
+def compare_precisions(m, h1, shift, precisions, iters, dims):
+    """Energy, rho* and scaling dimensions of the same tensors in several contraction
+    precisions; differences against the first one listed."""
+    ref = None
+    for prec in precisions:
+        mm = sweep.GpuMera([(u.clone(), w.clone()) for u, w in m.layers], (m.si[0].clone(), m.si[1].clone()),
+                           m.rho_star.clone())
+        sweep.initial_fixed_point(mm, iters, prec)
+        e = sweep.energy(mm, h1, shift)
+        d = None
+        if dims > 0:
+            d, _, _ = scaling.scaling_dimensions(
+                mm.si[0], mm.si[1], k=dims, precision=prec,
+                progress=lambda n: print(f"# {prec}: {n} ascends", file=sys.stderr, flush=True))
+            d = np.asarray(d)
+        rec = {"precision": prec, "energy": e}
+        if d is not None:
+            rec["scaling_dimensions"] = [round(float(x), 9) for x in d]
+        if ref is None:
+            ref = (e, mm.rho_star.clone(), d)
+        else:
+            rec["dE"] = abs(e - ref[0])
+            rec["rho_rel_err"] = float((mm.rho_star - ref[1]).norm() / ref[1].norm())
+            if d is not None:
+                rec["max_dDelta"] = float(np.abs(d - ref[2]).max())
+        print(json.dumps(rec), flush=True)
+        del mm
+        torch.cuda.empty_cache()
 
 
 if __name__ == "__main__":

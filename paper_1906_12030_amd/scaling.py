@@ -14,8 +14,10 @@ import torch
 from . import ops
 
 
-def scaling_dimensions(u: torch.Tensor, w: torch.Tensor, k: int = 12, precision="fp64", tol=1e-10):
-    """The k eigenvalues of A with largest modulus and Delta = -log2|lambda|, sorted by |lambda|."""
+def scaling_dimensions(u: torch.Tensor, w: torch.Tensor, k: int = 12, precision="fp64", tol=1e-10,
+                       progress=None):
+    """The k eigenvalues of A with largest modulus and Delta = -log2|lambda|, sorted by |lambda|.
+    progress (optional) is called with the number of matrix-vector products every 25 of them."""
     layer = ops.Layer(u, w)
     d = layer.din
     if layer.dout != d:
@@ -26,6 +28,8 @@ def scaling_dimensions(u: torch.Tensor, w: torch.Tensor, k: int = 12, precision=
 
     def mv(x):
         calls[0] += 1
+        if progress is not None and calls[0] % 25 == 0:
+            progress(calls[0])
         xt = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(dev).reshape((d,) * 6)
         y = ops.ascend(layer, xt, "avg", precision)
         return y.reshape(-1).cpu().numpy()

@@ -1,0 +1,61 @@
+"""Precision form against the FP64 oracle at chi = 16 (seeded, not optimised).
+
+Reference values (energy, norm, purity and 512 entries of rho*) come from
+tests/golden/precision_chi16.json, written by the oracle alone.  The GPU computes
+the same quantities with FP64, FP32 and split-bf16 contractions: rho* by 30 power
+iterations from the maximally mixed density (in FP32 / split bf16 one
+iterative-refinement cycle: one FP64 residual, 29 reduced-precision corrections),
+the energy by FP64 descent and trace.  From this cold start the correction is
+O(1), so the reduced-precision rho* carries the contraction rounding; warm-started
+sweeps reach the FP64 fixed point (the benchmark's dE_eval).  The errors are
+printed for the record; the bounds are about ten times the measured errors.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1906_12030_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = json.load(open(os.path.join(HERE, "golden", "precision_chi16.json")))
+
+# bounds on |dE| and on max |drho| / max |rho| over the sample
+BOUNDS = {"fp64": (1e-12, 1e-10), "fp32": (1e-6, 1e-5), "bf16x3": (1e-6, 1e-5)}
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_12030_amd import ops, sweep
+    return ops, sweep
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_precision_form_vs_oracle_chi16(mods, prec):
+    ops, sweep = mods
+    r = GOLD["recipe"]
+    print(f"precision form chi={r['chi']} {prec}", flush=True, file=sys.stderr)
+    layers, si = I.init_mera(r["chi"], r["transitional_layers"], r["seed"])
+    m = sweep.GpuMera(layers, si)
+    h1, shift = ops.tfim_hamiltonian(1.0)
+    sweep.initial_fixed_point(m, r["power_iterations"], prec)
+    e = sweep.energy(m, h1, shift)
+    rho = m.rho_star.reshape(-1)
+    idx = torch.tensor(GOLD["rho_sample_index"], device=rho.device)
+    sample = rho[idx].cpu().numpy()
+    ref = np.array(GOLD["rho_sample"])
+    drho = float(np.abs(sample - ref).max() / np.abs(ref).max())
+    dfro = abs(float(rho.norm()) - GOLD["rho_fro"]) / GOLD["rho_fro"]
+    dpur = abs(float(rho @ rho) - GOLD["rho_purity"]) / GOLD["rho_purity"]
+    de = abs(e - GOLD["energy"])
+    print(f"  {prec}: |dE| = {de:.3e}  rho* sample {drho:.3e}  ||rho*|| {dfro:.3e}  purity {dpur:.3e}",
+          flush=True, file=sys.stderr)
+    be, br = BOUNDS[prec]
+    assert de < be and drho < br and dfro < br and dpur < 2 * br, (de, drho, dfro, dpur)
