@@ -222,3 +222,32 @@ def test_sliced_descend_matches_unsliced(ops, prec):
     # same algorithm, different slice shapes: equal up to the reduced-precision rounding of the
     # correction (far from convergence after 12 steps the correction is not small)
     assert rel(host(r2), host(r1)) < (1e-14 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("frac", [0.0, 0.5])
+def test_sliced_descend_large_tile_chi16(ops, frac):
+    """Sliced split-bf16 descend at chi = 16, where every chi^8 / chi^9 step runs on the
+    large-tile kernel with the sliced leg outermost in its intermediates: workspace at the
+    minimum (one fine-leg value per slice) and half-way to the full size."""
+    from paper_1906_12030_amd import _lib
+    d = 16
+    u, w, rho, h = _case(d, d, 7)
+    say(f"sliced large-tile descend chi=16 frac={frac}")
+    layer = ops.Layer(gpu(u), gpu(w))
+    full = ops.descend(layer, gpu(rho), "AVG", "bf16x3")
+    ref64 = ops.descend(layer, gpu(rho), "AVG", "fp64")
+    q = ops.PRECISIONS["bf16x3"]
+    lo = _lib.mera_workspace_bytes_min(_lib.MERA_OP_DESCEND, d, d, q, _lib.MERA_AVG)
+    hi = _lib.load().mera_workspace_bytes(_lib.MERA_OP_DESCEND, d, d, q, _lib.MERA_AVG)
+    nb = int(lo + frac * (hi - lo))
+    assert nb < hi
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    base = (ws.data_ptr() + 255) & ~255
+    out = torch.empty((d,) * 6, dtype=torch.float64, device="cuda")
+    r = gpu(rho)
+    st = _lib.mera_descend(layer.c(), r.data_ptr(), out.data_ptr(), _lib.MERA_AVG, q, base, nb,
+                           torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    torch.cuda.synchronize()
+    assert float((out - full).norm() / full.norm()) < 1e-5
+    assert float((out - ref64).norm() / ref64.norm()) < 1e-5
