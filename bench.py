@@ -92,8 +92,8 @@ def env_call_rates(m, h1, precision, ops, sweep, lib):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chi", type=int, default=24)
     ap.add_argument("--layers", type=int, default=3)
     ap.add_argument("--iters", type=int, default=30)
@@ -198,6 +198,7 @@ def main():
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of this build",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    import numpy as np
     import torch
 
     from paper_1906_12030_amd import _lib, ops, sweep
@@ -229,8 +230,11 @@ def main():
     e_mixed = None
     e_first = None
     phases = {}
+    each = []
     for k in range(args.steps):
-        e, c = sweep.sweep(m, h1, shift, args.iters, prec, timings=phases)
+        tk = time.perf_counter()
+        e, c = sweep.sweep(m, h1, shift, args.iters, prec, timings=phases)  # synchronises
+        each.append(time.perf_counter() - tk)
         e_mixed = e
         if k == 0:
             e_first = e
@@ -353,6 +357,9 @@ def main():
                    "chi": chi, "transitional_layers": T, "power_iterations": args.iters,
                    "contraction_precision": prec},
         "sweep_s_mixed": round(t_mixed, 4),
+        "sweep_s_mixed_each": [round(x, 4) for x in each],
+        "sweep_s_mixed_median": round(float(np.median(each)), 4),
+        "sweep_s_mixed_min": round(min(each), 4),
         "sweep_s_fp64": round(t_fp64, 4) if t_fp64 else None,
         "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3) if t_fp64 else None,
         "sweep_s_fp32_contractions": round(t_fp32, 4) if t_fp32 else None,
