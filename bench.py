@@ -135,8 +135,20 @@ def cpu_baseline(chi: int, seed: int) -> dict:
         cores = max(int(d.get("num_threads", 1)) for d in threadpool_info()) if threadpool_info() else os.cpu_count()
     except Exception:  # pragma: no cover
         cores = os.cpu_count()
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:  # pragma: no cover
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = ", ".join(f"{d.get('internal_api')} {d.get('version')}" for d in threadpool_info()
+                         if d.get("user_api") == "blas") or None
+    except Exception:  # pragma: no cover
+        blas = None
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "seconds": dt,
+            "seconds": dt, "nproc": os.cpu_count(), "cpu_model": cpu_model, "blas": blas,
             "sample": f"oracle D_L at chi={chi} with the first fine leg fixed to one value "
                       f"(1/{chi} of a left-window descend, {flops:.3e} flop in the GPU schedule's count)"}
 
