@@ -99,6 +99,9 @@ def main(argv=None):
     ap.add_argument("--grow-from", default=None)
     ap.add_argument("--dims", type=int, default=0)
     ap.add_argument("--log", default=None)
+    ap.add_argument("--compare-sweeps", type=int, default=0,
+                    help="with --compare-precisions: also run this many sweeps from the final state in each "
+                         "precision and compare the FP64-evaluated energies (optimisation outcome)")
     ap.add_argument("--compare-precisions", default=None,
                     help="comma list, e.g. fp64,fp32,bf16x3: at the final state, rho* (30 warm-started "
                          "iterations), energy and (with --dims) scaling dimensions in each precision")
@@ -142,17 +145,40 @@ def main(argv=None):
         d, lam, calls = scaling.scaling_dimensions(m.si[0], m.si[1], k=a.dims)
         print(json.dumps({"scaling_dimensions": [round(float(x), 6) for x in d], "matvecs": calls}), flush=True)
     if a.compare_precisions:
-        compare_precisions(m, h1, shift, a.compare_precisions.split(","), a.iters, a.dims)
+        compare_precisions(m, h1, shift, a.compare_precisions.split(","), a.iters, a.dims, a.compare_sweeps)
     return e
 
 
-def compare_precisions(m, h1, shift, precisions, iters, dims):
+def _copy(m):
+    return sweep.GpuMera([(u.clone(), w.clone()) for u, w in m.layers], (m.si[0].clone(), m.si[1].clone()),
+                         m.rho_star.clone())
+
+
+def compare_precisions(m, h1, shift, precisions, iters, dims, nsweeps=0):
     """Energy, rho* and scaling dimensions of the same tensors in several contraction
-    precisions; differences against the first one listed."""
+    precisions; differences against the first one listed.  With nsweeps > 0, also the
+    optimisation outcome: nsweeps sweeps from the same state in each precision, the
+    resulting tensors evaluated in FP64 (rho* by iters warm-started FP64 iterations,
+    FP64 descent and trace)."""
+    if nsweeps > 0:
+        eref = None
+        for prec in precisions:
+            mm = _copy(m)
+            for _ in range(nsweeps):
+                sweep.sweep(mm, h1, shift, iters, prec)
+            sweep.initial_fixed_point(mm, iters, "fp64")
+            e = sweep.energy(mm, h1, shift)
+            rec = {"precision": prec, "sweeps_from_state": nsweeps, "energy_fp64_eval": e}
+            if eref is None:
+                eref = e
+            else:
+                rec["dE"] = abs(e - eref)
+            print(json.dumps(rec), flush=True)
+            del mm
+            torch.cuda.empty_cache()
     ref = None
     for prec in precisions:
-        mm = sweep.GpuMera([(u.clone(), w.clone()) for u, w in m.layers], (m.si[0].clone(), m.si[1].clone()),
-                           m.rho_star.clone())
+        mm = _copy(m)
         sweep.initial_fixed_point(mm, iters, prec)
         e = sweep.energy(mm, h1, shift)
         d = None
