@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--fp64-env-steps", type=int, default=1,
+                    help="sweeps timed with the fixed point in the benchmark precision and FP64 environments")
     ap.add_argument("--fp32-steps", type=int, default=1,
                     help="sweeps timed with FP32-MFMA contractions (the other reduced-precision form)")
     ap.add_argument("--seed", type=int, default=0)
@@ -317,6 +319,23 @@ def main():
         print(f"# fp32 sweep: {t_fp32:.3f} s/sweep, e = {e_fp32:.12f}", file=sys.stderr, flush=True)
         del m32
 
+    # ---- split-bf16 fixed point with FP64 ascent and environments (FP64 update directions) ----
+    t_fpenv = None
+    e_fpenv = None
+    if args.fp64_env_steps > 0 and prec != "fp64":
+        mfe = sweep.GpuMera(start_state["layers"], start_state["si"], start_state["rho_star"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.fp64_env_steps):
+            e, c = sweep.sweep(mfe, h1, shift, args.iters, prec, env_precision="fp64")
+            if k == 0:
+                e_fpenv = float(e.item()) + shift
+        torch.cuda.synchronize()
+        t_fpenv = (time.perf_counter() - t0) / args.fp64_env_steps
+        print(f"# {prec} fixed point + fp64 environments: {t_fpenv:.3f} s/sweep, e = {e_fpenv:.12f}",
+              file=sys.stderr, flush=True)
+        del mfe
+
     # ---- energy evaluation at the final tensors: mixed pipeline vs FP64 pipeline ----
     def eval_energy(precision):
         mm = sweep.GpuMera([(u.clone(), w.clone()) for u, w in m.layers], (m.si[0].clone(), m.si[1].clone()),
@@ -374,6 +393,10 @@ def main():
         "sweep_s_mixed_min": round(min(each), 4),
         "sweep_s_fp64": round(t_fp64, 4) if t_fp64 else None,
         "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3) if t_fp64 else None,
+        "sweep_s_mixed_fixed_point_fp64_env": round(t_fpenv, 4) if t_fpenv else None,
+        "speedup_mixed_fixed_point_fp64_env_vs_fp64": round(t_fp64 / t_fpenv, 3) if (t_fpenv and t_fp64) else None,
+        "dE_one_sweep_mixed_fixed_point_fp64_env_vs_fp64":
+            abs(e_fpenv - e_fp64) if (e_fpenv is not None and e_fp64 is not None) else None,
         "sweep_s_fp32_contractions": round(t_fp32, 4) if t_fp32 else None,
         "speedup_fp32_vs_fp64": round(t_fp64 / t_fp32, 3) if (t_fp32 and t_fp64) else None,
         "dE_one_sweep_fp32_vs_fp64": abs(e_fp32 - e_fp64) if (e_fp32 is not None and e_fp64 is not None) else None,

@@ -104,7 +104,9 @@ def main(argv=None):
                          "precision and compare the FP64-evaluated energies (optimisation outcome)")
     ap.add_argument("--compare-precisions", default=None,
                     help="comma list, e.g. fp64,fp32,bf16x3: at the final state, rho* (30 warm-started "
-                         "iterations), energy and (with --dims) scaling dimensions in each precision")
+                         "iterations), energy and (with --dims) scaling dimensions in each precision; "
+                         "for --compare-sweeps an entry a/b runs the fixed point in a and the "
+                         "environments in b")
     a = ap.parse_args(argv)
     if not torch.cuda.is_available():
         raise SystemExit("a GPU is required")
@@ -164,8 +166,9 @@ def compare_precisions(m, h1, shift, precisions, iters, dims, nsweeps=0):
         eref = None
         for prec in precisions:
             mm = _copy(m)
+            fp, _, ep = prec.partition("/")  # "bf16x3/fp64": fixed point in bf16x3, environments in FP64
             for _ in range(nsweeps):
-                sweep.sweep(mm, h1, shift, iters, prec)
+                sweep.sweep(mm, h1, shift, iters, fp, env_precision=ep or None)
             sweep.initial_fixed_point(mm, iters, "fp64")
             e = sweep.energy(mm, h1, shift)
             rec = {"precision": prec, "sweeps_from_state": nsweeps, "energy_fp64_eval": e}
@@ -177,7 +180,7 @@ def compare_precisions(m, h1, shift, precisions, iters, dims, nsweeps=0):
             del mm
             torch.cuda.empty_cache()
     ref = None
-    for prec in precisions:
+    for prec in [p for p in precisions if "/" not in p]:
         mm = _copy(m)
         sweep.initial_fixed_point(mm, iters, prec)
         e = sweep.energy(mm, h1, shift)

@@ -98,8 +98,13 @@ def _si_operators(m: GpuMera, h_top, si_levels, precision):
 
 
 def sweep(m: GpuMera, h1: torch.Tensor, shift: float, iters=30, precision="fp64", si_levels=1,
-          timings: dict | None = None):
-    """One optimisation sweep; returns the energy per site (device tensor + shift)."""
+          timings: dict | None = None, env_precision: str | None = None):
+    """One optimisation sweep; returns the energy per site (device tensor + shift).
+
+    ``precision`` selects the contractions of every step; ``env_precision`` (default:
+    the same) overrides it for the ascent of h and the environments, so that e.g. only
+    the fixed-point iteration runs in split bf16 while the update directions are FP64."""
+    envp = precision if env_precision is None else env_precision
     ev = {}
 
     def mark(name):
@@ -109,19 +114,19 @@ def sweep(m: GpuMera, h1: torch.Tensor, shift: float, iters=30, precision="fp64"
             ev[name] = e
 
     mark("start")
-    hs = ascend_chain(m, h1, precision)
+    hs = ascend_chain(m, h1, envp)
     mark("ascend")
-    h_si = _si_operators(m, hs[-1], si_levels, precision)
+    h_si = _si_operators(m, hs[-1], si_levels, envp)
     si = m.si_layer()
     eu = None
     for hk in h_si:
-        e = ops.env_u(si, hk, m.rho_star, "avg", precision)
+        e = ops.env_u(si, hk, m.rho_star, "avg", envp)
         eu = e if eu is None else eu.add_(e)
     m.si[0] = ops.update_u(eu)
     si = m.si_layer()
     ew = None
     for hk in h_si:
-        e = ops.env_w(si, hk, m.rho_star, "avg", precision)
+        e = ops.env_w(si, hk, m.rho_star, "avg", envp)
         ew = e if ew is None else ew.add_(e)
     m.si[1] = ops.update_w(ew)
     mark("si_update")
@@ -130,9 +135,9 @@ def sweep(m: GpuMera, h1: torch.Tensor, shift: float, iters=30, precision="fp64"
     rho = m.rho_star
     for t in reversed(range(len(m.layers))):
         lay = m.layer(t)
-        m.layers[t][0] = ops.update_u(ops.env_u(lay, hs[t], rho, "avg", precision))
+        m.layers[t][0] = ops.update_u(ops.env_u(lay, hs[t], rho, "avg", envp))
         lay = m.layer(t)
-        m.layers[t][1] = ops.update_w(ops.env_w(lay, hs[t], rho, "avg", precision))
+        m.layers[t][1] = ops.update_w(ops.env_w(lay, hs[t], rho, "avg", envp))
         lay = m.layer(t)
         rho = ops.descend(lay, rho, "avg", "fp64")
     mark("transitional")
