@@ -99,8 +99,11 @@ def parse():
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--fp64-env-steps", type=int, default=1,
-                    help="sweeps timed with the fixed point in the benchmark precision and FP64 environments")
+    ap.add_argument("--env-precision", default="fp64", choices=["fp32", "bf16x3", "fp64"],
+                    help="contractions of the ascent and the environments in the timed sweeps (the "
+                         "fixed-point iteration uses --precision)")
+    ap.add_argument("--all-reduced-steps", type=int, default=1,
+                    help="sweeps timed with every contraction in --precision (environments included)")
     ap.add_argument("--fp32-steps", type=int, default=1,
                     help="sweeps timed with FP32-MFMA contractions (the other reduced-precision form)")
     ap.add_argument("--seed", type=int, default=0)
@@ -231,8 +234,9 @@ def main():
           file=sys.stderr, flush=True)
     sweep.initial_fixed_point(m, args.iters, prec)
     torch.cuda.synchronize()
+    envp = args.env_precision
     for k in range(args.warmup):
-        sweep.sweep(m, h1, shift, args.iters, prec)
+        sweep.sweep(m, h1, shift, args.iters, prec, env_precision=envp)
         torch.cuda.synchronize()
         print(f"# warmup sweep {k} done", file=sys.stderr, flush=True)
     start_state = m.state_dict()
@@ -247,7 +251,7 @@ def main():
     each = []
     for k in range(args.steps):
         tk = time.perf_counter()
-        e, c = sweep.sweep(m, h1, shift, args.iters, prec, timings=phases)  # synchronises
+        e, c = sweep.sweep(m, h1, shift, args.iters, prec, timings=phases, env_precision=envp)  # synchronises
         each.append(time.perf_counter() - tk)
         e_mixed = e
         if k == 0:
@@ -272,7 +276,6 @@ def main():
     all_ms = sum(r[3] for r in recs)
     all_f = sum(r[2] for r in recs)
 
-    env = env_rates(recs, code, ops, _lib)
     # per-step totals of the timed sweeps (stderr only)
     steps = {}
     for r in recs:
@@ -319,22 +322,27 @@ def main():
         print(f"# fp32 sweep: {t_fp32:.3f} s/sweep, e = {e_fp32:.12f}", file=sys.stderr, flush=True)
         del m32
 
-    # ---- split-bf16 fixed point with FP64 ascent and environments (FP64 update directions) ----
-    t_fpenv = None
-    e_fpenv = None
-    if args.fp64_env_steps > 0 and prec != "fp64":
-        mfe = sweep.GpuMera(start_state["layers"], start_state["si"], start_state["rho_star"])
+    # ---- every contraction in the benchmark precision (environments included) ----
+    t_red = None
+    e_red = None
+    env = None
+    if args.all_reduced_steps > 0 and envp != prec:
+        mr = sweep.GpuMera(start_state["layers"], start_state["si"], start_state["rho_star"])
+        _lib.mera_profile_begin()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(args.fp64_env_steps):
-            e, c = sweep.sweep(mfe, h1, shift, args.iters, prec, env_precision="fp64")
+        for k in range(args.all_reduced_steps):
+            e, c = sweep.sweep(mr, h1, shift, args.iters, prec)
             if k == 0:
-                e_fpenv = float(e.item()) + shift
+                e_red = float(e.item()) + shift
         torch.cuda.synchronize()
-        t_fpenv = (time.perf_counter() - t0) / args.fp64_env_steps
-        print(f"# {prec} fixed point + fp64 environments: {t_fpenv:.3f} s/sweep, e = {e_fpenv:.12f}",
-              file=sys.stderr, flush=True)
-        del mfe
+        t_red = (time.perf_counter() - t0) / args.all_reduced_steps
+        _, recs_red = _lib.mera_profile_end()
+        env = env_rates(recs_red, code, ops, _lib)
+        print(f"# all contractions {prec}: {t_red:.3f} s/sweep, e = {e_red:.12f}", file=sys.stderr, flush=True)
+        del mr
+    else:
+        env = env_rates(recs, code, ops, _lib)
 
     # ---- energy evaluation at the final tensors: mixed pipeline vs FP64 pipeline ----
     def eval_energy(precision):
@@ -380,23 +388,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": prec,
+        "dtype": prec if envp == prec else f"{prec}/{envp}",
         "data": "synthetic (seeded QR-of-Gaussian MERA tensors, exact TFIM h=1)",
         "config": {"workload": f"scale-invariant binary MERA sweep, critical TFIM, chi={chi}, "
                                f"{T} transitional layers ({'-'.join(str(a) for a, _ in sweep.layer_dims(m)[:-1])}-{chi}) "
-                               f"+ SI layer, {args.iters} power iterations, seed {args.seed}",
+                               f"+ SI layer, {args.iters} power iterations, seed {args.seed}; fixed-point "
+                               f"contractions {prec} (FP64 refinement), ascent and environments {envp}",
                    "chi": chi, "transitional_layers": T, "power_iterations": args.iters,
-                   "contraction_precision": prec},
+                   "fixed_point_precision": prec, "environment_precision": envp},
         "sweep_s_mixed": round(t_mixed, 4),
         "sweep_s_mixed_each": [round(x, 4) for x in each],
         "sweep_s_mixed_median": round(float(np.median(each)), 4),
         "sweep_s_mixed_min": round(min(each), 4),
         "sweep_s_fp64": round(t_fp64, 4) if t_fp64 else None,
         "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3) if t_fp64 else None,
-        "sweep_s_mixed_fixed_point_fp64_env": round(t_fpenv, 4) if t_fpenv else None,
-        "speedup_mixed_fixed_point_fp64_env_vs_fp64": round(t_fp64 / t_fpenv, 3) if (t_fpenv and t_fp64) else None,
-        "dE_one_sweep_mixed_fixed_point_fp64_env_vs_fp64":
-            abs(e_fpenv - e_fp64) if (e_fpenv is not None and e_fp64 is not None) else None,
+        "sweep_s_all_contractions_reduced": round(t_red, 4) if t_red else None,
+        "speedup_all_reduced_vs_fp64": round(t_fp64 / t_red, 3) if (t_red and t_fp64) else None,
+        "dE_one_sweep_all_reduced_vs_fp64": abs(e_red - e_fp64) if (e_red is not None and e_fp64 is not None) else None,
         "sweep_s_fp32_contractions": round(t_fp32, 4) if t_fp32 else None,
         "speedup_fp32_vs_fp64": round(t_fp64 / t_fp32, 3) if (t_fp32 and t_fp64) else None,
         "dE_one_sweep_fp32_vs_fp64": abs(e_fp32 - e_fp64) if (e_fp32 is not None and e_fp64 is not None) else None,
