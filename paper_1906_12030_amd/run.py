@@ -91,6 +91,8 @@ def main(argv=None):
     ap.add_argument("--sweeps", type=int, default=100)
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--env-precision", default=None, choices=["fp64", "fp32", "bf16x3"],
+                    help="contractions of the ascent and the environments (default: --precision)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--si-levels", type=int, default=1)
     ap.add_argument("--every", type=int, default=10)
@@ -128,7 +130,7 @@ def main(argv=None):
     t0 = time.perf_counter()
     e = float("nan")
     for k in range(start, start + a.sweeps):
-        ek, c = sweep.sweep(m, h1, shift, a.iters, a.precision, a.si_levels)
+        ek, c = sweep.sweep(m, h1, shift, a.iters, a.precision, a.si_levels, env_precision=a.env_precision)
         if (k + 1) % a.every == 0 or k + 1 == start + a.sweeps:
             e = float(ek.item()) + c
             dt = (time.perf_counter() - t0) / (k + 1 - start)
