@@ -273,6 +273,35 @@ def ascend_placement(u, w, op, placement):
     return _einsum(subs + [fine], ops + [op], coarse)
 
 
+def _einsum_fixed(subs, ops, out, pos, index):
+    """The same network with output leg `pos` fixed to `index`: a unit vector on
+    that leg is one more operand, so the sum itself is unchanged."""
+    leg = out[pos]
+    d = next(t.shape[s.index(leg)] for s, t in zip(subs, ops) if leg in s)
+    unit = np.zeros(d)
+    unit[index] = 1.0
+    return _einsum(subs + [leg], ops + [unit], out[:pos] + out[pos + 1:])
+
+
+def ascend_placement_slice(u, w, op, placement, index):
+    """A_P(op) with its first coarse (ket) leg fixed to `index` (a 1/d share of A_P)."""
+    subs, ops, coarse, fine = _network_operands(u, w, placement)
+    return _einsum_fixed(subs + [fine], ops + [op], coarse, 0, index)
+
+
+def descend_by_slices(u, w, rho):
+    """D = (D_L + D_R)/2 assembled from slices over the first fine ket leg, so that
+    no intermediate holds more than a 1/d share of the network (large d)."""
+    din = u.shape[0]
+    out = np.empty((din,) * 6)
+    for k in range(din):
+        out[k] = descend_placement_slice(u, w, rho, "L", k)
+    for k in range(din):
+        out[k] += descend_placement_slice(u, w, rho, "R", k)
+    out *= 0.5
+    return out
+
+
 def descend(u, w, rho):
     """Averaged descending superoperator D = (D_L + D_R) / 2."""
     return 0.5 * (descend_placement(u, w, rho, "L") + descend_placement(u, w, rho, "R"))
@@ -310,6 +339,27 @@ def env_contribution(u, w, h, rho, placement, copy):
     ket, _, _, _ = _cone(placement)
     subs, ops, coarse, fine = _network_operands(u, w, placement, skip_ket=copy)
     return _einsum(subs + [coarse, _transpose_label(fine)], ops + [rho, h], ket[copy])
+
+
+def env_contribution_slice(u, w, h, rho, placement, copy, pos, index):
+    """env_contribution with leg `pos` of the environment fixed to `index`."""
+    ket, _, _, _ = _cone(placement)
+    subs, ops, coarse, fine = _network_operands(u, w, placement, skip_ket=copy)
+    return _einsum_fixed(subs + [coarse, _transpose_label(fine)], ops + [rho, h], ket[copy], pos, index)
+
+
+def env_slice(u, w, h, rho, which, placement, index):
+    """Env_u[index] (which='u': first lower leg fixed) or Env_w[:, :, index] (which='w':
+    the upper leg fixed, which slices the density) of placement L, R or AVG: the same
+    sum of contributions as env_u / env_w."""
+    places = ("L", "R") if placement == "AVG" else (placement,)
+    scale = 0.5 if placement == "AVG" else 1.0
+    copies = ("uL", "uR") if which == "u" else ("wL", "wC", "wR")
+    out = 0.0
+    for p in places:
+        for copy in copies:
+            out = out + env_contribution_slice(u, w, h, rho, p, copy, 0 if which == "u" else 2, index)
+    return scale * out
 
 
 def env_u(u, w, h, rho, placement="AVG"):
@@ -367,26 +417,27 @@ def identity_density(d):
     return (np.eye(n) / n).reshape((d,) * 6)
 
 
-def power_iteration_step(u, w, rho):
-    """rho <- D(rho), then symmetrised and normalised to unit trace."""
+def power_iteration_step(u, w, rho, sliced=False):
+    """rho <- D(rho), then symmetrised and normalised to unit trace (sliced: D is
+    evaluated slice by slice, for large d)."""
     d = rho.shape[0]
     n = d ** 3
-    r = descend(u, w, rho).reshape(n, n)
+    r = (descend_by_slices if sliced else descend)(u, w, rho).reshape(n, n)
     r = 0.5 * (r + r.T)
     r = r / np.trace(r)
     return r.reshape(rho.shape)
 
 
-def fixed_point_rho(u, w, rho0, iters):
+def fixed_point_rho(u, w, rho0, iters, sliced=False):
     rho = rho0
     for _ in range(iters):
-        rho = power_iteration_step(u, w, rho)
+        rho = power_iteration_step(u, w, rho, sliced)
     return rho
 
 
-def fixed_point_residual(u, w, rho):
+def fixed_point_residual(u, w, rho, sliced=False):
     """||D(rho) - rho||_F / ||rho||_F."""
-    r = descend(u, w, rho)
+    r = (descend_by_slices if sliced else descend)(u, w, rho)
     return float(np.linalg.norm(r - rho) / np.linalg.norm(rho))
 
 
@@ -414,17 +465,17 @@ def ascend_chain(state: MeraState, h1):
     return hs
 
 
-def descend_chain(state: MeraState, rho_top):
+def descend_chain(state: MeraState, rho_top, sliced=False):
     """[rho_1, ..., rho_{T+1}] with rho_{T+1} = rho_top and rho_t = D_t(rho_{t+1})."""
     rhos = [rho_top]
     for u, w in reversed(state.layers):
-        rhos.append(descend(u, w, rhos[-1]))
+        rhos.append((descend_by_slices if sliced else descend)(u, w, rhos[-1]))
     return rhos[::-1]
 
 
-def energy(state: MeraState, h1, shift=0.0):
+def energy(state: MeraState, h1, shift=0.0, sliced=False):
     """Energy per site tr(h_1 rho_1) + shift, rho_1 descended from rho*."""
-    rho1 = descend_chain(state, state.rho_star)[0]
+    rho1 = descend_chain(state, state.rho_star, sliced)[0]
     return trace_product(h1, rho1) + shift
 
 
