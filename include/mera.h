@@ -62,7 +62,7 @@ typedef enum {
   MERA_EWORKSPACE = 3,  /* workspace smaller than mera_workspace_bytes() */
   MERA_EDEVICE = 4,     /* a HIP call failed */
   MERA_ENUMERIC = 5,    /* non-finite data, or a polar iteration that did not converge */
-  MERA_ENOTCONV = 6     /* reserved */
+  MERA_ENOTCONV = 6     /* a tolerance was not reached within the iteration budget */
 } mera_status;
 
 typedef enum { MERA_LEFT = 0, MERA_RIGHT = 1, MERA_AVG = 2 } mera_placement;
@@ -115,16 +115,22 @@ int mera_env_w(const mera_layer* layer, const double* h_d, const double* rho_d, 
 /* SVD update (Sec. II.C, Fig. 5): out = -U V^T where env = U S V^T is the
  * environment blocked as a rows x cols matrix (rows = lower legs, cols = upper
  * legs; rows >= cols), i.e. minus the orthogonal polar factor of env.
- * FP64 only, computed on the device by a Newton-Schulz polar iteration.
- * Synchronises `hip_stream` (it reads convergence flags on the host).  Returns
- * MERA_ENUMERIC for non-finite input or when the iteration does not reach an
- * isometry (rank-deficient env); `out_d` is still written.  iters_out (host
- * pointer, nullable) receives the number of iterations used. */
-int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* out_d,
-                      int32_t* iters_out, void* ws_d, size_t ws_bytes, void* hip_stream);
+ * FP64 only, computed on the device by the Newton-Schulz polar iteration
+ * X <- X (3 I - X^T X) / 2 from env / ||env||_F; the host reads the change per
+ * iteration in batches of four (one stream synchronisation per batch).
+ * sv_d (device, nullable, cols doubles) receives the singular values of env,
+ * largest first: the eigenvalues of the symmetric positive semidefinite X^T env
+ * at convergence (Householder tridiagonalisation and bisection on the device);
+ * needs cols <= 4080 (MERA_ESHAPE otherwise).
+ * Synchronises `hip_stream`.  Returns MERA_ENUMERIC for a zero or non-finite
+ * env, or when the iteration does not reach an isometry within 100 steps
+ * (rank-deficient env: the polar factor is not unique); `out_d` (and sv_d) are
+ * still written. */
+int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* out_d, double* sv_d,
+                      void* ws_d, size_t ws_bytes, void* hip_stream);
 
-/* Fixed point of the scale-invariant descending superoperator (Sec. II.B):
- * `iters` power-iteration steps rho <- D_AVG(rho), rho <- (rho + rho^T)/2,
+/* Fixed point of the scale-invariant descending superoperator by iteration
+ * (Sec. II.B): power-iteration steps rho <- D_AVG(rho), rho <- (rho + rho^T)/2,
  * rho <- rho/tr(rho), with the symmetrisation and renormalisation in FP64.
  * MERA_FP64 runs exactly that.  MERA_FP32 / MERA_BF16X3 run it in
  * iterative-refinement form, in cycles of up to 30 steps: one FP64 residual
@@ -133,10 +139,19 @@ int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* o
  * steps equals L power-iteration steps; the reduced-precision error is
  * proportional to ||delta|| rather than ||rho||, so repeated calls converge to
  * the FP64 fixed point.  rho_d (d^6) holds the warm start on entry and the
- * result on exit.
- * resid_d (device, nullable, 1 double) receives ||rho_k - rho_{k-1}||_F /
- * ||rho_k||_F of the last step.  layer->din must equal layer->dout. */
-int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int precision,
+ * result on exit.  layer->din must equal layer->dout.
+ * Residual: res(rho) = ||D(rho) - rho||_F / ||rho||_F with D in FP64.
+ * tol = 0: exactly `iters` steps, fully asynchronous.
+ * tol > 0: at most `iters` steps; res is measured at every FP64 descend of the
+ *   current density (every step in MERA_FP64, at the start of every cycle
+ *   otherwise) and the call returns that density as soon as res <= tol; if the
+ *   budget runs out, one more FP64 descend measures the density returned and
+ *   the call returns MERA_ENOTCONV when res > tol (rho_d still holds the last
+ *   iterate).  Synchronises the stream at every measurement.
+ * resid_d (device, nullable, 1 double) receives res of the density returned
+ * (with tol = 0 this costs one more FP64 descend).
+ * Errors: MERA_EINVAL also for a negative or non-finite tol. */
+int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, double tol, int precision,
                          double* resid_d, void* ws_d, size_t ws_bytes, void* hip_stream);
 
 /* Energy (Sec. II.B): e = tr(h rho) = sum_ij h_ij rho_ji for n x n matrices

@@ -59,8 +59,8 @@ def load() -> ctypes.CDLL:
     lib.mera_descend.argtypes = [lp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
     lib.mera_env_u.argtypes = [lp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
     lib.mera_env_w.argtypes = [lp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
-    lib.mera_polar_update.argtypes = [vp, i64, i64, vp, ctypes.POINTER(i32), vp, sz, vp]
-    lib.mera_fixed_point_rho.argtypes = [lp, vp, i32, ctypes.c_int, vp, vp, sz, vp]
+    lib.mera_polar_update.argtypes = [vp, i64, i64, vp, vp, vp, sz, vp]
+    lib.mera_fixed_point_rho.argtypes = [lp, vp, i32, dbl, ctypes.c_int, vp, vp, sz, vp]
     lib.mera_energy.argtypes = [vp, vp, i64, vp, vp]
     lib.mera_tfim_hamiltonian.argtypes = [dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.mera_workspace_bytes.argtypes = [ctypes.c_int, i32, i32, ctypes.c_int, ctypes.c_int]
@@ -116,14 +116,13 @@ def mera_env_w(layer, h_d, rho_d, env_d, placement, precision, ws_d, ws_bytes, s
     return load().mera_env_w(ctypes.byref(layer), h_d, rho_d, env_d, placement, precision, ws_d, ws_bytes, stream)
 
 
-def mera_polar_update(env_d, rows, cols, out_d, ws_d, ws_bytes, stream):
-    it = ctypes.c_int32(0)
-    st = load().mera_polar_update(env_d, rows, cols, out_d, ctypes.byref(it), ws_d, ws_bytes, stream)
-    return st, it.value
+def mera_polar_update(env_d, rows, cols, out_d, sv_d, ws_d, ws_bytes, stream):
+    return load().mera_polar_update(env_d, rows, cols, out_d, sv_d, ws_d, ws_bytes, stream)
 
 
-def mera_fixed_point_rho(layer, rho_d, iters, precision, resid_d, ws_d, ws_bytes, stream):
-    return load().mera_fixed_point_rho(ctypes.byref(layer), rho_d, iters, precision, resid_d, ws_d, ws_bytes, stream)
+def mera_fixed_point_rho(layer, rho_d, iters, tol, precision, resid_d, ws_d, ws_bytes, stream):
+    return load().mera_fixed_point_rho(ctypes.byref(layer), rho_d, iters, float(tol), precision, resid_d,
+                                       ws_d, ws_bytes, stream)
 
 
 def mera_energy(h_d, rho_d, n, e_d, stream):

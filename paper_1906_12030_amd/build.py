@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["contract.hip", "contract_b3.hip", "contract_b3x.hip", "aux.hip", "peak.hip", "mera_api.hip"]
+SOURCES = ["contract.hip", "contract_b3.hip", "contract_b3x.hip", "aux.hip", "peak.hip", "symeig.hip", "mera_api.hip"]
 LIB = os.path.join(HERE, "libmera.so")
 
 # Packed-FP32 instructions are disabled: the compiler must not form v_pk_*_f32 from float code.

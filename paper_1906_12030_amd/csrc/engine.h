@@ -94,4 +94,12 @@ hipError_t launch_axpby(const double* x, double* y, double a, double b, int64_t 
 hipError_t launch_scale_by_rsqrt(const double* x, double* y, const double* nrm2_d, int64_t n,
                                  hipStream_t s);
 
+// ---- symmetric eigenvalues (symeig.hip) ----
+// Eigenvalues of the symmetric part of the n x n row-major matrix `a`, largest
+// first, clamped at zero from below (used for singular values from X^T Y).
+// Destroys `a`; dg and off hold n doubles each.  1 <= n <= kSymEigMaxOrder.
+constexpr int64_t kSymEigMaxOrder = 4080;
+hipError_t launch_sym_eigvals_desc(double* a, int64_t n, double* dg, double* off, double* out,
+                                   hipStream_t s);
+
 }  // namespace mera

@@ -543,8 +543,14 @@ int run_checked(Ctx& cx, void* ws, size_t ws_bytes, void* stream, F&& body) {
 // Polar update by the Newton-Schulz iteration X <- X (3 I - X^T X) / 2 started
 // from Y / ||Y||_F (all singular values in (0, 1]), which converges to the
 // orthogonal polar factor U V^T of Y = U S V^T.
+// The host reads the per-iteration changes in batches of kPolarBatch (one
+// stream synchronisation per batch); iterations past convergence inside a batch
+// leave the isometry unchanged up to rounding (quadratic convergence).
+constexpr int kPolarMaxIter = 100;
+constexpr int kPolarBatch = 4;
+
 struct PolarWs {
-  double *x, *xn, *g, *partial, *scal;
+  double *x, *xn, *g, *partial, *scal, *dg, *off;
 };
 PolarWs polar_layout(Ctx& cx, int64_t rows, int64_t cols) {
   PolarWs p;
@@ -552,11 +558,81 @@ PolarWs polar_layout(Ctx& cx, int64_t rows, int64_t cols) {
   p.xn = cx.take_d(rows * cols);
   p.g = cx.take_d(cols * cols);
   p.partial = cx.take_d(mera::kReduceBlocks);
-  p.scal = cx.take_d(4);
+  p.scal = cx.take_d(2 + kPolarBatch);
+  p.dg = cx.take_d(cols);   // singular values: tridiagonal form of X^T Y
+  p.off = cx.take_d(cols);
   return p;
 }
 
-constexpr int kPolarMaxIter = 100;
+// Newton-Schulz polar iteration on the buffers of `p` (see polar_layout), then
+// out = -X and, when sv_d is given, the eigenvalues of X^T Y (the singular
+// values of Y, largest first).  Synchronises `s`.
+int polar_run(PolarWs p, const double* env_d, int64_t rows, int64_t cols, double* out_d, double* sv_d,
+              hipStream_t s) {
+  LabelDims dims;
+  dims.d['a'] = rows;
+  dims.d['b'] = cols;
+  dims.d['c'] = cols;
+  const int64_t n = rows * cols;
+  double host[2 + kPolarBatch];
+  auto fail = [&](hipError_t e, const char* what) {
+    set_err(std::string("polar ") + what + ": " + hipGetErrorString(e));
+    return MERA_EDEVICE;
+  };
+  hipError_t e;
+  if ((e = mera::launch_reduce(4, env_d, nullptr, n, p.partial, p.scal, s))) return fail(e, "norm");
+  if ((e = hipMemcpyAsync(host, p.scal, sizeof(double), hipMemcpyDeviceToHost, s))) return fail(e, "copy");
+  if ((e = hipStreamSynchronize(s))) return fail(e, "sync");
+  if (!std::isfinite(host[0]) || host[0] <= 0.0) {
+    if ((e = mera::launch_fill(out_d, 0.0, n, s))) return fail(e, "fill");
+    if (sv_d && (e = mera::launch_fill(sv_d, 0.0, cols, s))) return fail(e, "fill");
+    if ((e = hipStreamSynchronize(s))) return fail(e, "sync");
+    set_err("polar: environment is zero or not finite");
+    return MERA_ENUMERIC;
+  }
+  if ((e = mera::launch_scale_by_rsqrt(env_d, p.x, p.scal, n, s))) return fail(e, "scale");
+  int it = 0;
+  bool conv = false, bad = false;
+  const double thr = 1e-13 * std::sqrt((double)cols);
+  while (it < kPolarMaxIter && !conv && !bad) {
+    const int batch = std::min(kPolarBatch, kPolarMaxIter - it);
+    for (int b = 0; b < batch; ++b) {
+      // X <- X (3 I - X^T X) / 2
+      if ((e = mera::contract(Arith::F64, dims, p.x, "ab", p.x, "ac", p.g, "bc", true, 1.0, 0.0, s)))
+        return fail(e, "gram");
+      if ((e = mera::launch_scale(p.x, p.xn, 1.5, n, s))) return fail(e, "scale");
+      if ((e = mera::contract(Arith::F64, dims, p.x, "ab", p.g, "bc", p.xn, "ac", true, -0.5, 1.0, s)))
+        return fail(e, "update");
+      if ((e = mera::launch_reduce(1, p.xn, p.x, n, p.partial, p.scal + 2 + b, s))) return fail(e, "diff");
+      std::swap(p.x, p.xn);
+    }
+    if ((e = hipMemcpyAsync(host + 2, p.scal + 2, batch * sizeof(double), hipMemcpyDeviceToHost, s)))
+      return fail(e, "copy");
+    if ((e = hipStreamSynchronize(s))) return fail(e, "sync");
+    for (int b = 0; b < batch && !conv && !bad; ++b) {
+      ++it;
+      if (!std::isfinite(host[2 + b])) bad = true;
+      else if (std::sqrt(host[2 + b]) < thr) conv = true;
+    }
+  }
+  // out = -X; singular values from X^T Y; then check that X reached an isometry: ||X||_F^2 = cols
+  if ((e = mera::launch_scale(p.x, out_d, -1.0, n, s))) return fail(e, "out");
+  if (sv_d) {
+    if ((e = mera::contract(Arith::F64, dims, p.x, "ab", env_d, "ac", p.g, "bc", true, 1.0, 0.0, s)))
+      return fail(e, "x^T y");
+    if ((e = mera::launch_sym_eigvals_desc(p.g, cols, p.dg, p.off, sv_d, s))) return fail(e, "eigenvalues");
+  }
+  if ((e = mera::launch_reduce(4, p.x, nullptr, n, p.partial, p.scal + 1, s))) return fail(e, "fro");
+  if ((e = hipMemcpyAsync(host, p.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s)))
+    return fail(e, "copy");
+  if ((e = hipStreamSynchronize(s))) return fail(e, "sync");
+  if (!conv || !(std::fabs(host[0] - (double)cols) < 1e-8 * (double)cols)) {
+    set_err("polar: iteration did not reach an isometry (rank-deficient or non-finite environment)");
+    return MERA_ENUMERIC;
+  }
+  return MERA_OK;
+}
+
 
 }  // namespace
 
@@ -827,14 +903,18 @@ int mera_energy(const double* h_d, const double* rho_d, int64_t n, double* e_d, 
   return MERA_OK;
 }
 
-int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* out_d,
-                      int32_t* iters_out, void* ws_d, size_t ws_bytes, void* hip_stream) {
+int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* out_d, double* sv_d,
+                      void* ws_d, size_t ws_bytes, void* hip_stream) {
   if (!env_d || !out_d) {
     set_err("null tensor pointer");
     return MERA_EINVAL;
   }
   if (rows < 1 || cols < 1 || rows < cols || rows * cols >= (int64_t(1) << 31)) {
     set_err("polar needs rows >= cols >= 1");
+    return MERA_ESHAPE;
+  }
+  if (sv_d && cols > mera::kSymEigMaxOrder) {
+    set_err("polar: singular values are available for cols <= " + std::to_string(mera::kSymEigMaxOrder));
     return MERA_ESHAPE;
   }
   Ctx dry;
@@ -853,62 +933,10 @@ int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* o
   cx.base = static_cast<char*>(ws_d);
   cx.s = static_cast<hipStream_t>(hip_stream);
   PolarWs p = polar_layout(cx, rows, cols);
-  LabelDims dims;
-  dims.d['a'] = rows;
-  dims.d['b'] = cols;
-  dims.d['c'] = cols;
-  hipStream_t s = cx.s;
-  const int64_t n = rows * cols;
-  double host[2];
-  auto fail = [&](hipError_t e, const char* what) {
-    set_err(std::string("polar ") + what + ": " + hipGetErrorString(e));
-    return MERA_EDEVICE;
-  };
-  hipError_t e;
-  if ((e = mera::launch_reduce(4, env_d, nullptr, n, p.partial, p.scal, s))) return fail(e, "norm");
-  if ((e = hipMemcpyAsync(host, p.scal, sizeof(double), hipMemcpyDeviceToHost, s))) return fail(e, "copy");
-  if ((e = hipStreamSynchronize(s))) return fail(e, "sync");
-  if (!std::isfinite(host[0]) || host[0] <= 0.0) {
-    if ((e = mera::launch_fill(out_d, 0.0, n, s))) return fail(e, "fill");
-    hipStreamSynchronize(s);
-    set_err("polar: environment is zero or not finite");
-    return MERA_ENUMERIC;
-  }
-  if ((e = mera::launch_scale_by_rsqrt(env_d, p.x, p.scal, n, s))) return fail(e, "scale");
-  int it = 0;
-  bool conv = false;
-  for (it = 1; it <= kPolarMaxIter; ++it) {
-    if ((e = mera::contract(Arith::F64, dims, p.x, "ab", p.x, "ac", p.g, "bc", true, 1.0, 0.0, s)))
-      return fail(e, "gram");
-    if ((e = mera::launch_scale(p.x, p.xn, 1.5, n, s))) return fail(e, "scale");
-    if ((e = mera::contract(Arith::F64, dims, p.x, "ab", p.g, "bc", p.xn, "ac", true, -0.5, 1.0, s)))
-      return fail(e, "update");
-    if ((e = mera::launch_reduce(1, p.xn, p.x, n, p.partial, p.scal + 1, s))) return fail(e, "diff");
-    std::swap(p.x, p.xn);
-    if ((e = hipMemcpyAsync(host + 1, p.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s)))
-      return fail(e, "copy");
-    if ((e = hipStreamSynchronize(s))) return fail(e, "sync");
-    if (!std::isfinite(host[1])) break;
-    if (std::sqrt(host[1]) < 1e-13 * std::sqrt((double)cols)) {
-      conv = true;
-      break;
-    }
-  }
-  if (iters_out) *iters_out = it > kPolarMaxIter ? kPolarMaxIter : it;
-  // out = -X; then check that X reached an isometry: ||X||_F^2 = cols
-  if ((e = mera::launch_scale(p.x, out_d, -1.0, n, s))) return fail(e, "out");
-  if ((e = mera::launch_reduce(4, p.x, nullptr, n, p.partial, p.scal + 2, s))) return fail(e, "fro");
-  if ((e = hipMemcpyAsync(host, p.scal + 2, sizeof(double), hipMemcpyDeviceToHost, s)))
-    return fail(e, "copy");
-  if ((e = hipStreamSynchronize(s))) return fail(e, "sync");
-  if (!conv || !(std::fabs(host[0] - (double)cols) < 1e-8 * (double)cols)) {
-    set_err("polar: iteration did not reach an isometry (rank-deficient or non-finite environment)");
-    return MERA_ENUMERIC;
-  }
-  return MERA_OK;
+  return polar_run(p, env_d, rows, cols, out_d, sv_d, cx.s);
 }
 
-int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int precision,
+int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, double tol, int precision,
                          double* resid_d, void* ws_d, size_t ws_bytes, void* hip_stream) {
   OpTag tag(MERA_OP_FIXED_POINT);
   int st = check_layer(si);
@@ -918,8 +946,8 @@ int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int
     set_err("fixed point needs din == dout");
     return MERA_ESHAPE;
   }
-  if (!rho_d || iters < 0) {
-    set_err("null density or negative iteration count");
+  if (!rho_d || iters < 0 || !(tol >= 0.0) || !std::isfinite(tol)) {
+    set_err("null density, negative iteration count or tolerance not a finite number >= 0");
     return MERA_EINVAL;
   }
   const int64_t d = si->din;
@@ -935,15 +963,19 @@ int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int
   // which in exact arithmetic equals L power-iteration steps
   // (rho + sum_{k<L} D^k r = D^L rho) while the low-precision products only
   // act on the correction, so their error scales with ||delta||, not ||rho||.
+  // Every FP64 descend of the current density also gives its residual
+  // ||D64(rho) - rho||_F / ||rho||_F; with tol > 0 the call stops at the first
+  // density whose residual is <= tol.
   constexpr int kRefineCycle = 30;
+  const bool want_end_residual = resid_d != nullptr || tol > 0.0;
+  int status = MERA_OK;
   int S = 1;  // slices of the chi^7 intermediates (chosen below from ws_bytes)
   auto body = [&](Ctx& c) {
     double* tmp = c.take_d(nn);
-    double* prev = resid_d ? c.take_d(nn) : nullptr;
     double* r = lp != Arith::F64 ? c.take_d(nn) : nullptr;
     double* dl = lp != Arith::F64 ? c.take_d(nn) : nullptr;
     double* partial = c.take_d(mera::kReduceBlocks);
-    double* scal = c.take_d(4);
+    double* scal = c.take_d(4);  // trace, ||D(rho) - rho||^2, ||rho||^2, residual
     const size_t mark = c.off;
     // one descend in arithmetic a; the descend workspace is reused every time
     auto D = [&](Arith a, const double* in, double* out) {
@@ -954,30 +986,58 @@ int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int
       c.ar = save;
     };
     if (c.dry) {  // size the workspace for both arithmetics; count one iteration
-      if (iters > 0) {
+      if (iters > 0 || want_end_residual) {
         D(Arith::F64, rho_d, tmp);
         const size_t hi = c.off;
-        if (lp != Arith::F64) D(lp, rho_d, tmp);
+        if (lp != Arith::F64 && iters > 0) D(lp, rho_d, tmp);
         c.off = std::max(hi, c.off);
       }
       return;
     }
-    auto finish = [&](double* next, bool last) {
-      // rho <- (next + next^T) / tr(next), in FP64
+    // residual of the current density from d64 = D64(rho_d), into scal[3]
+    auto measure = [&](const double* d64) {
+      c.check(mera::launch_reduce(1, d64, rho_d, nn, partial, scal + 1, c.s), "diff");
+      c.check(mera::launch_reduce(4, rho_d, nullptr, nn, partial, scal + 2, c.s), "norm");
+      c.check(mera::launch_sqrt_ratio(scal + 1, scal + 2, scal + 3, c.s), "ratio");
+    };
+    // host read of the residual (synchronises); false on a device error or NaN
+    auto meets_tol = [&]() {
+      double h = NAN;
+      c.check(hipMemcpyAsync(&h, scal + 3, sizeof(double), hipMemcpyDeviceToHost, c.s), "copy");
+      c.check(hipStreamSynchronize(c.s), "sync");
+      return c.err == hipSuccess && h <= tol;
+    };
+    // rho <- (next + next^T) / tr(next), in FP64
+    auto finish = [&](double* next) {
       c.check(mera::launch_reduce(2, next, nullptr, n, partial, scal, c.s), "trace");
-      if (resid_d && last) c.check(hipMemcpyAsync(prev, rho_d, nn * 8, hipMemcpyDeviceToDevice, c.s), "copy");
       c.check(mera::launch_sym_normalize(next, rho_d, n, scal, c.s), "symmetrise");
     };
+    bool measured = false;  // scal[3] holds the residual of rho_d as it is now
+    bool met = false;
     if (lp == Arith::F64) {
       for (int it = 0; it < iters; ++it) {
         D(Arith::F64, rho_d, tmp);
-        finish(tmp, it == iters - 1);
+        if (tol > 0.0) {
+          measure(tmp);
+          if (meets_tol()) {
+            measured = met = true;
+            break;
+          }
+        }
+        finish(tmp);
       }
     } else {
       int done = 0;
       while (done < iters) {
         const int L = std::min(kRefineCycle, iters - done);
         D(Arith::F64, rho_d, tmp);                                          // D64(rho)
+        if (tol > 0.0) {
+          measure(tmp);
+          if (meets_tol()) {
+            measured = met = true;
+            break;
+          }
+        }
         c.check(mera::launch_scale(tmp, r, 1.0, nn, c.s), "copy");          // r = D64(rho)
         c.check(mera::launch_axpby(rho_d, r, -1.0, 1.0, nn, c.s), "resid");  // r -= rho
         c.check(mera::launch_scale(r, dl, 1.0, nn, c.s), "copy");           // delta = r
@@ -988,17 +1048,18 @@ int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int
         }
         c.check(mera::launch_axpby(rho_d, dl, 1.0, 1.0, nn, c.s), "update");  // rho + delta
         done += L;
-        finish(dl, done >= iters);
+        finish(dl);
       }
     }
-    if (resid_d) {
-      if (iters == 0) {
-        c.check(mera::launch_fill(resid_d, 0.0, 1, c.s), "fill");
-      } else {
-        c.check(mera::launch_reduce(1, rho_d, prev, nn, partial, scal + 1, c.s), "diff");
-        c.check(mera::launch_reduce(4, rho_d, nullptr, nn, partial, scal + 2, c.s), "norm");
-        c.check(mera::launch_sqrt_ratio(scal + 1, scal + 2, resid_d, c.s), "ratio");
-      }
+    if (!measured && want_end_residual) {  // residual of the density returned
+      D(Arith::F64, rho_d, tmp);
+      measure(tmp);
+      if (tol > 0.0) met = meets_tol();
+    }
+    if (resid_d) c.check(mera::launch_scale(scal + 3, resid_d, 1.0, 1, c.s), "residual");
+    if (tol > 0.0 && !met && c.err == hipSuccess) {
+      set_err("fixed point: residual above tol after the iteration budget");
+      status = MERA_ENOTCONV;
     }
   };
   S = choose_slices(cx, d, ws_bytes, [&](Ctx& c, int s) {
@@ -1009,8 +1070,8 @@ int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, int
     set_err("workspace too small even with the chi^7 intermediates sliced");
     return MERA_EWORKSPACE;
   }
-  int rc = run_checked(cx, ws_d, ws_bytes, hip_stream, body);
-  return rc;
+  const int rc = run_checked(cx, ws_d, ws_bytes, hip_stream, body);
+  return rc != MERA_OK ? rc : status;
 }
 
 int mera_tfim_hamiltonian(double field, double* h_host, double* shift_host) {
@@ -1097,7 +1158,6 @@ size_t mera_workspace_bytes(int op, int32_t din, int32_t dout, int precision, in
       const int64_t n = (int64_t)din * din * din;
       const bool refine = precision != MERA_FP64;
       cx.take_d(n * n);                  // tmp
-      cx.take_d(n * n);                  // prev (residual output)
       if (refine) {
         cx.take_d(n * n);                // r
         cx.take_d(n * n);                // delta
@@ -1140,7 +1200,7 @@ size_t mera_workspace_bytes_min(int op, int32_t din, int32_t dout, int precision
   }
   const int64_t n = (int64_t)din * din * din;
   const bool refine = precision != MERA_FP64;
-  for (int i = 0; i < (refine ? 4 : 2); ++i) cx.take_d(n * n);
+  for (int i = 0; i < (refine ? 3 : 1); ++i) cx.take_d(n * n);
   cx.take_d(mera::kReduceBlocks);
   cx.take_d(4);
   const size_t mark = cx.off;

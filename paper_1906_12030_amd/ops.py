@@ -144,17 +144,21 @@ def env_w(layer: Layer, h: torch.Tensor, rho: torch.Tensor, placement="avg", pre
     return out
 
 
-def polar_update(env: torch.Tensor, rows: int, cols: int, out=None, check=True):
-    """-U V^T of env blocked as rows x cols (Sec. II.C, Fig. 5).  Returns (out, iterations, status)."""
+def polar_update(env: torch.Tensor, rows: int, cols: int, out=None, check=True, want_sv=False):
+    """-U V^T of env blocked as rows x cols (Sec. II.C, Fig. 5).
+
+    Returns (out, singular values or None, status)."""
     env = _dev(env)
     if out is None:
         out = torch.empty(env.shape, dtype=torch.float64, device=env.device)
+    sv = torch.empty(cols, dtype=torch.float64, device=env.device) if want_sv else None
     nb = _lib.mera_workspace_bytes(_lib.MERA_OP_POLAR, rows, cols, 0, 0)
     ws, wsb = WORKSPACE.get(nb, env.device)
-    st, iters = _lib.mera_polar_update(env.data_ptr(), rows, cols, out.data_ptr(), ws, wsb, _stream(env.device))
+    st = _lib.mera_polar_update(env.data_ptr(), rows, cols, out.data_ptr(),
+                                sv.data_ptr() if sv is not None else None, ws, wsb, _stream(env.device))
     if check:
         _lib.check(st, "mera_polar_update")
-    return out, iters, st
+    return out, sv, st
 
 
 def update_u(env: torch.Tensor, check=True) -> torch.Tensor:
@@ -167,17 +171,23 @@ def update_w(env: torch.Tensor, check=True) -> torch.Tensor:
     return polar_update(env, din * din, dout, check=check)[0]
 
 
-def fixed_point_rho(si: Layer, rho: torch.Tensor, iters: int, precision="fp64", want_residual=False):
-    """In place: iters power-iteration steps of the scale-invariant D (Sec. II.B)."""
+def fixed_point_rho(si: Layer, rho: torch.Tensor, iters: int, precision="fp64", want_residual=False,
+                    tol: float = 0.0, check=True):
+    """In place: at most iters power-iteration steps of the scale-invariant D (Sec. II.B).
+
+    tol > 0 stops at the first density with ||D(rho) - rho||_F / ||rho||_F <= tol.
+    Returns (rho, residual of the returned rho as a device tensor or None, status)."""
     if not (rho.is_cuda and rho.dtype == torch.float64 and rho.is_contiguous()):
         raise ValueError("rho must be a contiguous float64 GPU tensor (it is updated in place)")
     q = _prec(precision)
     resid = torch.zeros(1, dtype=torch.float64, device=rho.device) if want_residual else None
     ws, wsb = WORKSPACE.for_op(_lib.MERA_OP_FIXED_POINT, si.din, si.dout, q, _lib.MERA_AVG, rho.device)
-    _lib.check(_lib.mera_fixed_point_rho(si.c(), rho.data_ptr(), int(iters), q,
-                                         resid.data_ptr() if resid is not None else None,
-                                         ws, wsb, _stream(rho.device)), "mera_fixed_point_rho")
-    return rho, resid
+    st = _lib.mera_fixed_point_rho(si.c(), rho.data_ptr(), int(iters), float(tol), q,
+                                   resid.data_ptr() if resid is not None else None,
+                                   ws, wsb, _stream(rho.device))
+    if check:
+        _lib.check(st, "mera_fixed_point_rho")
+    return rho, resid, st
 
 
 def energy(h: torch.Tensor, rho: torch.Tensor) -> torch.Tensor:

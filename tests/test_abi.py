@@ -35,6 +35,7 @@ def test_strerror(lib):
     for st in range(7):
         assert lib.mera_strerror(st)
     assert b"unknown" in lib.mera_strerror(99)
+    assert b"reserved" not in lib.mera_strerror(_lib.MERA_ENOTCONV)
 
 
 def _layer(din, dout, nonnull=True):
@@ -52,12 +53,16 @@ def test_invalid_arguments_rejected_before_device(lib):
     assert _lib.mera_ascend(_layer(0, 4), fake, fake, 2, 0, fake, 1 << 40, None) == _lib.MERA_ESHAPE
     assert _lib.mera_env_u(_layer(3, 3), fake, None, fake, 2, 0, fake, 1 << 40, None) == _lib.MERA_EINVAL
     assert _lib.mera_env_w(_layer(3, 10), fake, fake, fake, 2, 0, fake, 1 << 40, None) == _lib.MERA_ESHAPE
-    assert _lib.mera_fixed_point_rho(_layer(3, 4), fake, 5, 0, None, fake, 1 << 40, None) == _lib.MERA_ESHAPE
-    assert _lib.mera_fixed_point_rho(_layer(3, 3), fake, -1, 0, None, fake, 1 << 40, None) == _lib.MERA_EINVAL
-    st, _ = _lib.mera_polar_update(fake, 4, 9, fake, fake, 1 << 40, None)
-    assert st == _lib.MERA_ESHAPE
-    st, _ = _lib.mera_polar_update(None, 9, 4, fake, fake, 1 << 40, None)
-    assert st == _lib.MERA_EINVAL
+    assert _lib.mera_fixed_point_rho(_layer(3, 4), fake, 5, 0.0, 0, None, fake, 1 << 40, None) == _lib.MERA_ESHAPE
+    assert _lib.mera_fixed_point_rho(_layer(3, 3), fake, -1, 0.0, 0, None, fake, 1 << 40, None) == _lib.MERA_EINVAL
+    # the tolerance must be a finite number >= 0
+    for bad in (-1e-9, float("nan"), float("inf")):
+        assert _lib.mera_fixed_point_rho(_layer(3, 3), fake, 5, bad, 0, None, fake, 1 << 40, None) == _lib.MERA_EINVAL
+    assert _lib.mera_polar_update(fake, 4, 9, fake, None, fake, 1 << 40, None) == _lib.MERA_ESHAPE
+    assert _lib.mera_polar_update(None, 9, 4, fake, None, fake, 1 << 40, None) == _lib.MERA_EINVAL
+    # singular values are limited to the order the device eigensolver handles
+    assert _lib.mera_polar_update(fake, 5000, 4100, fake, fake, fake, 1 << 40, None) == _lib.MERA_ESHAPE
+    assert b"4080" in lib.mera_last_error()
     assert _lib.mera_energy(fake, fake, 0, fake, None) == _lib.MERA_ESHAPE
     assert lib.mera_last_error()
 
@@ -72,11 +77,11 @@ def test_workspace_too_small_and_misaligned(lib):
     fneed = _lib.mera_workspace_bytes_min(_lib.MERA_OP_FIXED_POINT, 4, 4, 2, 2)
     assert 0 < fneed < _lib.mera_workspace_bytes(_lib.MERA_OP_FIXED_POINT, 4, 4, 2, 2)
     # far below the sliced minimum: rejected before any device work
-    assert _lib.mera_fixed_point_rho(_layer(4, 4), fake, 3, 2, None, fake, fneed // 4, None) == _lib.MERA_EWORKSPACE
+    assert _lib.mera_fixed_point_rho(_layer(4, 4), fake, 3, 0.0, 2, None, fake, fneed // 4, None) == _lib.MERA_EWORKSPACE
+    assert _lib.mera_fixed_point_rho(_layer(4, 4), fake, 3, 1e-10, 2, fake, fake, fneed // 4, None) == _lib.MERA_EWORKSPACE
     assert _lib.mera_descend(_layer(4, 4), fake, fake, 2, 0, fake + 8, need, None) == _lib.MERA_EINVAL
     npol = _lib.mera_workspace_bytes(_lib.MERA_OP_POLAR, 16, 4, 0, 0)
-    st, _ = _lib.mera_polar_update(fake, 16, 4, fake, fake, npol - 1, None)
-    assert st == _lib.MERA_EWORKSPACE
+    assert _lib.mera_polar_update(fake, 16, 4, fake, fake, fake, npol - 1, None) == _lib.MERA_EWORKSPACE
 
 
 def test_workspace_grows_with_bond_dimension(lib):

@@ -113,12 +113,13 @@ def test_large_chi12_descend(ops):
     assert rel(a, O.ascend(u, w, h)) < TOL["fp64"]
 
 
-@pytest.mark.parametrize("rows,cols", [(4, 4), (16, 4), (16, 16), (64, 8), (81, 81), (256, 16), (576, 24)])
+@pytest.mark.parametrize("rows,cols", [(4, 4), (16, 4), (16, 16), (64, 8), (81, 81), (256, 16), (576, 24),
+                                       (576, 576), (1024, 1024)])
 def test_polar_update(ops, rows, cols):
     rng = np.random.default_rng(rows + 7 * cols)
     y = rng.standard_normal((rows, cols))
     say(f"polar rows={rows} cols={cols}")
-    out, iters, st = ops.polar_update(gpu(y), rows, cols)
+    out, sv, st = ops.polar_update(gpu(y), rows, cols, want_sv=True)
     got = host(out)
     ref, s = O.polar_update_matrix(y)
     # the polar factor's condition number is about 1/sigma_min (relative)
@@ -126,16 +127,23 @@ def test_polar_update(ops, rows, cols):
     assert st == 0
     assert np.abs(got - ref).max() < 1e-13 * cond * max(1.0, np.sqrt(cols))
     assert np.abs(got.T @ got - np.eye(cols)).max() < 1e-13
+    # singular values (largest first) against LAPACK: backward-stable eigenvalues of
+    # X^T Y are accurate to a few ulps of sigma_max times the order
+    assert np.abs(host(sv) - s).max() < 1e-14 * cols * s[0]
 
 
 def test_polar_rejects_rank_deficient(ops):
     rng = np.random.default_rng(5)
     y = rng.standard_normal((16, 4)) @ np.diag([1.0, 1.0, 1.0, 0.0])
-    out, iters, st = ops.polar_update(gpu(y), 16, 4, check=False)
+    out, sv, st = ops.polar_update(gpu(y), 16, 4, check=False, want_sv=True)
     assert st == 5  # MERA_ENUMERIC
+    # the singular values are still written: the zero one is resolved to the scale of sigma_max
+    s = np.linalg.svd(y, compute_uv=False)
+    assert np.abs(host(sv) - s).max() < 1e-12 * s[0]
     z = np.zeros((9, 3))
-    out, iters, st = ops.polar_update(gpu(z), 9, 3, check=False)
+    out, sv, st = ops.polar_update(gpu(z), 9, 3, check=False, want_sv=True)
     assert st == 5
+    assert np.all(host(sv) == 0.0) and np.all(host(out) == 0.0)
 
 
 @pytest.mark.parametrize("d", [2, 3, 4])
@@ -147,11 +155,12 @@ def test_fixed_point(ops, d):
     ref = O.fixed_point_rho(u, w, rho0, 25)
     layer = ops.Layer(gpu(u), gpu(w))
     r = gpu(rho0)
-    _, res = ops.fixed_point_rho(layer, r, 25, "fp64", want_residual=True)
+    _, res, st = ops.fixed_point_rho(layer, r, 25, "fp64", want_residual=True)
+    assert st == 0
     assert rel(host(r), ref) < 1e-12
-    prev = O.fixed_point_rho(u, w, rho0, 24)
-    want = np.linalg.norm(ref - prev) / np.linalg.norm(ref)
-    assert abs(host(res)[0] - want) < 1e-10 + 1e-6 * want
+    # residual of the returned density, ||D(rho) - rho||_F / ||rho||_F (Sec. II.B)
+    want = O.fixed_point_residual(u, w, ref)
+    assert abs(host(res)[0] - want) < 1e-12 + 1e-8 * want
 
 
 def test_energy_and_hamiltonian(ops):
@@ -216,7 +225,7 @@ def test_sliced_descend_matches_unsliced(ops, prec):
     r1 = gpu(O.identity_density(din))
     r2 = gpu(O.identity_density(din))
     ops.fixed_point_rho(layer, r1, 12, prec)
-    st = _lib.mera_fixed_point_rho(layer.c(), r2.data_ptr(), 12, q, None, base2, nf,
+    st = _lib.mera_fixed_point_rho(layer.c(), r2.data_ptr(), 12, 0.0, q, None, base2, nf,
                                    torch.cuda.current_stream().cuda_stream)
     assert st == 0
     # same algorithm, different slice shapes: equal up to the reduced-precision rounding of the
@@ -251,3 +260,32 @@ def test_sliced_descend_large_tile_chi16(ops, frac):
     torch.cuda.synchronize()
     assert float((out - full).norm() / full.norm()) < 1e-5
     assert float((out - ref64).norm() / ref64.norm()) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_fixed_point_tolerance(ops, prec):
+    """tol > 0: the call stops at the first density whose residual is <= tol and returns
+    MERA_ENOTCONV when the budget runs out first (Sec. II.B, iterative methods)."""
+    rng = np.random.default_rng(91)
+    d = 3
+    u, w = I.random_layer(rng, d, d)
+    say(f"fixed point tolerance {prec}")
+    layer = ops.Layer(gpu(u), gpu(w))
+    # a budget too small for 1e-12: ENOTCONV, residual of the returned density reported
+    r = gpu(O.identity_density(d))
+    _, res, st = ops.fixed_point_rho(layer, r, 3, prec, want_residual=True, tol=1e-12, check=False)
+    assert st == 6  # MERA_ENOTCONV
+    got = host(r)
+    assert abs(host(res)[0] - O.fixed_point_residual(u, w, got)) < 1e-12
+    assert host(res)[0] > 1e-12
+    # a generous budget: stops with the residual at or below tol, and at or below it in the oracle
+    r = gpu(O.identity_density(d))
+    _, res, st = ops.fixed_point_rho(layer, r, 3000, prec, want_residual=True, tol=1e-10)
+    assert st == 0
+    got = host(r)
+    assert host(res)[0] <= 1e-10
+    assert O.fixed_point_residual(u, w, got) <= 1e-10 * (1 + 1e-6) + 1e-15
+    assert abs(np.trace(got.reshape(d ** 3, -1)) - 1.0) < 1e-13
+    # the same density as the FP64 oracle's after enough plain steps
+    ref = O.fixed_point_rho(u, w, O.identity_density(d), 3000)
+    assert rel(got, ref) < 1e-8
