@@ -43,8 +43,10 @@ PEAK = {  # MI355X published dense peaks, TFLOP/s
 }
 
 
-def env_rates(recs, code, ops, lib):
-    """Environment contraction launches (mera_env_u / mera_env_w) of the timed sweeps."""
+def env_rates(recs, code, ops, lib, precision):
+    """Environment contraction launches (mera_env_u / mera_env_w) of the timed sweeps, against
+    the roof of their own arithmetic: FP64 / FP32 MFMA peak, or for split bf16 the useful roof
+    (bf16 peak / 3) and the bf16 peak itself for the executed products (three per useful one)."""
     env_ops = (lib.MERA_OP_ENV_U, lib.MERA_OP_ENV_W)
     sel = [r for r in recs if r[4] in env_ops and r[1] == code]
     if not sel:
@@ -52,8 +54,14 @@ def env_rates(recs, code, ops, lib):
     f = sum(r[2] for r in sel)
     ms = sum(r[3] for r in sel)
     tf = f / (ms / 1e3) / 1e12
-    return {"launches": len(sel), "flops": f, "launch_ms": round(ms, 3), "tflops": round(tf, 3),
-            "frac_of_fp32_mfma_peak": round(tf / PEAK["fp32"], 4)}
+    out = {"precision": precision, "launches": len(sel), "flops": f, "launch_ms": round(ms, 3),
+           "tflops": round(tf, 3)}
+    if precision == "bf16x3":
+        out["frac_of_bf16x3_useful_roof"] = round(tf / (PEAK["bf16"] / 3.0), 4)
+        out["frac_of_bf16_mfma_peak_executed"] = round(3.0 * tf / PEAK["bf16"], 4)
+    else:
+        out[f"frac_of_{precision}_mfma_peak"] = round(tf / PEAK[precision], 4)
+    return out
 
 
 def env_call_rates(m, h1, precision, ops, sweep, lib):
@@ -98,7 +106,8 @@ def parse():
     ap.add_argument("--layers", type=int, default=3)
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "fp64"])
-    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=3,
+                    help="plain FP64 sweeps timed from the same state (their median is the ratio's denominator)")
     ap.add_argument("--env-precision", default="fp64", choices=["fp32", "bf16x3", "fp64"],
                     help="contractions of the ascent and the environments in the timed sweeps (the "
                          "fixed-point iteration uses --precision)")
@@ -106,6 +115,9 @@ def parse():
                     help="sweeps timed with every contraction in --precision (environments included)")
     ap.add_argument("--fp32-steps", type=int, default=1,
                     help="sweeps timed with FP32-MFMA contractions (the other reduced-precision form)")
+    ap.add_argument("--fp32-env-steps", type=int, default=1,
+                    help="sweeps timed with the fixed point in --precision and the ascent and environments "
+                         "on FP32 MFMA (FP64 kept for polar, renormalisation, transitional descents, energy)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--profile-only", action="store_true",
@@ -115,31 +127,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(chi: int, seed: int) -> dict:
-    """The FP64 oracle on a bounded sample of the same workload, on the host cores."""
-    import numpy as np
-
-    from oracle import mera_oracle as O
-    from paper_1906_12030_amd import inputs as I
-
-    rng = np.random.default_rng(seed)
-    u, w = I.random_layer(rng, chi, chi)
-    g = rng.standard_normal((chi ** 3, 64))
-    rho = (g @ g.T)
-    rho /= np.trace(rho)
-    rho = rho.reshape((chi,) * 6)
-    t0 = time.perf_counter()
-    flops = 0.0
-    O.descend_placement_slice(u, w, rho, "L", 0)
-    dt = time.perf_counter() - t0
-    # the work of that sample in the GPU schedule's own flop count (1/chi of a left-window descend)
-    from paper_1906_12030_amd import ops
-    flops = ops.flops("descend", chi, chi, "L") / chi
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max(int(d.get("num_threads", 1)) for d in threadpool_info()) if threadpool_info() else os.cpu_count()
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count()
+def _host_info():
     cpu_model = None
     try:
         with open("/proc/cpuinfo") as f:
@@ -148,31 +136,88 @@ def cpu_baseline(chi: int, seed: int) -> dict:
         pass
     try:
         from threadpoolctl import threadpool_info
-        blas = ", ".join(f"{d.get('internal_api')} {d.get('version')}" for d in threadpool_info()
+        info = threadpool_info()
+        blas = ", ".join(f"{d.get('internal_api')} {d.get('version')}" for d in info
                          if d.get("user_api") == "blas") or None
+        threads = max((int(d.get("num_threads", 1)) for d in info), default=os.cpu_count())
     except Exception:  # pragma: no cover
-        blas = None
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "seconds": dt, "nproc": os.cpu_count(), "cpu_model": cpu_model, "blas": blas,
-            "sample": f"oracle D_L at chi={chi} with the first fine leg fixed to one value "
-                      f"(1/{chi} of a left-window descend, {flops:.3e} flop in the GPU schedule's count)"}
+        blas, threads = None, os.cpu_count()
+    return cpu_model, blas, threads
 
 
-def cpu_thread_scan(chi: int, seed: int) -> list:
-    """Oracle throughput on one host thread and on all of them (the same 1/chi slice of
-    D_L at a smaller chi, so that the single-thread run stays short)."""
+def _oracle_inputs(chi, seed):
     import numpy as np
-    from threadpoolctl import threadpool_limits
 
-    from oracle import mera_oracle as O
     from paper_1906_12030_amd import inputs as I
-    from paper_1906_12030_amd import ops
 
     rng = np.random.default_rng(seed)
     u, w = I.random_layer(rng, chi, chi)
-    g = rng.standard_normal((chi ** 3, 64))
-    rho = (g @ g.T) / np.trace(g @ g.T)
-    rho = rho.reshape((chi,) * 6)
+    rho = I.random_density(rng, chi)
+    h = I.random_symmetric(rng, chi)
+    return u, w, rho, h
+
+
+def cpu_baseline(chi: int, seed: int, dims, iters: int, si_levels: int = 1) -> dict:
+    """The FP64 oracle on the host cores: measured on a bounded sample of the workload (one
+    1/chi slice of the left-window descend at chi), and its seconds per sweep extrapolated
+    from per-call times: a whole descend at chi = 2 chi slices (left and right windows); the
+    other calls at chi from their cost relative to the descend, measured on whole calls at
+    chi/2 (all AVG); the transitional layers' calls by the ratio of their executed flops to
+    the scale-invariant call's (the GPU schedule's own count)."""
+    from oracle import mera_oracle as O
+    from paper_1906_12030_amd import ops
+
+    u, w, rho, h = _oracle_inputs(chi, seed)
+    t0 = time.perf_counter()
+    O.descend_placement_slice(u, w, rho, "L", 0)
+    t_slice = time.perf_counter() - t0
+    del u, w, rho, h
+    flops = ops.flops("descend", chi, chi, "L") / chi  # that sample in the GPU schedule's count
+    chi0 = chi // 2
+    u0, w0, rho0, h0 = _oracle_inputs(chi0, seed)
+    calls0 = {}
+    for name, fn in (("ascend", lambda: O.ascend(u0, w0, h0)), ("descend", lambda: O.descend(u0, w0, rho0)),
+                     ("env_u", lambda: O.env_u(u0, w0, h0, rho0)), ("env_w", lambda: O.env_w(u0, w0, h0, rho0))):
+        t0 = time.perf_counter()
+        fn()
+        calls0[name] = time.perf_counter() - t0
+    t_descend = 2 * chi * t_slice
+    per_call = {k: t_descend * v / calls0["descend"] for k, v in calls0.items()}  # SI-layer calls at chi
+
+    def call(op, din, dout):
+        return per_call[op] * ops.flops(op, din, dout) / ops.flops(op, chi, chi)
+
+    trans = dims[:-1]
+    sweep_s = {"ascend": sum(call("ascend", a, b) for a, b in trans),
+               "si_update": si_levels * (per_call["env_u"] + per_call["env_w"])
+               + (si_levels - 1) * per_call["ascend"],
+               "fixed_point": iters * per_call["descend"],
+               "transitional": sum(call("env_u", a, b) + call("env_w", a, b) + call("descend", a, b)
+                                   for a, b in trans)}
+    cpu_model, blas, threads = _host_info()
+    return {"value": flops / t_slice / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "seconds": round(t_slice, 3), "nproc": os.cpu_count(), "cpu_model": cpu_model, "blas": blas,
+            "sample": f"oracle D_L at chi={chi} with the first fine leg fixed to one value "
+                      f"(1/{chi} of a left-window descend, {flops:.3e} flop in the GPU schedule's count)",
+            "sweep_s_extrapolated": round(sum(sweep_s.values()), 1),
+            "sweep_s_extrapolated_by_phase": {k: round(v, 1) for k, v in sweep_s.items()},
+            "per_call_s_extrapolated": {k: round(v, 2) for k, v in per_call.items()},
+            "extrapolation": f"descend at chi={chi} = 2 x {chi} slices of {t_slice:.2f} s; ascend, env_u, env_w "
+                             f"from their time relative to the descend at chi={chi0} (ascend {calls0['ascend']:.2f} s, "
+                             f"descend {calls0['descend']:.2f} s, env_u {calls0['env_u']:.2f} s, env_w "
+                             f"{calls0['env_w']:.2f} s); sweep = {iters} descends + the SI environments + the "
+                             f"transitional layers scaled by executed flops"}
+
+
+def cpu_thread_scan(chi: int, seed: int) -> list:
+    """Oracle throughput on one host thread and on all of them: the 1/chi slice of D_L at
+    the benchmark's chi (Sec. III.B compares thread counts; the paper used 1/16/32/64)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import mera_oracle as O
+    from paper_1906_12030_amd import ops
+
+    u, w, rho, _ = _oracle_inputs(chi, seed)
     flops = ops.flops("descend", chi, chi, "L") / chi
     out = []
     for threads in (1, os.cpu_count()):
@@ -207,6 +252,30 @@ def traffic_probe(args):
     torch.cuda.synchronize()
     print(json.dumps({"traffic_probe": True, "chi": chi, "precision": args.precision,
                       "copy_bytes": 8 << 27, "check": float(out.reshape(-1)[0].item())}))
+
+
+def evaluation_vs_oracle(args, h1, shift, sweep, prec):
+    """Energy of the seeded chi = 24 state (the benchmark's initial tensors) after args.iters
+    power iterations from the maximally mixed density, FP64 descent and trace, computed by the
+    mixed pipeline (fixed point in `prec` with FP64 refinement) and by plain FP64, against the
+    FP64 oracle value of tests/golden/fixed_point_chi24.json (written by the oracle alone)."""
+    path = os.path.join(ROOT, "tests", "golden", "fixed_point_chi24.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    r = g["recipe"]
+    if (r["chi"], r["transitional_layers"], r["seed"], r["power_iterations"]) != (
+            args.chi, args.layers, args.seed, args.iters):
+        return None
+    out = {"oracle_energy": g["energy"]}
+    for p in (prec, "fp64"):
+        mm = sweep.GpuMera.seeded(args.chi, args.layers, args.seed)
+        sweep.initial_fixed_point(mm, args.iters, p)
+        e = sweep.energy(mm, h1, shift)
+        out[f"energy_{p}"] = e
+        out[f"dE_{p}"] = abs(e - g["energy"])
+        del mm
+    return out
 
 
 def main():
@@ -289,60 +358,62 @@ def main():
         print(f"#   {lab:28s} a={ar} op={op} {n:5d} {ms:10.2f} {f / (ms / 1e3) / 1e12:8.1f}", file=sys.stderr)
     sys.stderr.flush()
 
-    # ---- plain FP64 sweep(s) from the same starting state, for the ratio ----
-    t_fp64 = None
-    e_fp64 = None
-    if args.fp64_steps > 0:
-        m64 = sweep.GpuMera(start_state["layers"], start_state["si"], start_state["rho_star"])
+    def timed_from_start(nsteps, precision, env_precision=None, profile=False):
+        """nsteps sweeps from the common starting state: per-sweep seconds, the energy after
+        the first sweep, and the profile records when asked for."""
+        mm = sweep.GpuMera(start_state["layers"], start_state["si"], start_state["rho_star"])
+        if profile:
+            _lib.mera_profile_begin()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.fp64_steps):
-            e, c = sweep.sweep(m64, h1, shift, args.iters, "fp64")
+        times, e_one = [], None
+        for k in range(nsteps):
+            tk = time.perf_counter()
+            e, c = sweep.sweep(mm, h1, shift, args.iters, precision, env_precision=env_precision)
+            e = float(e.item()) + shift  # synchronises
+            times.append(time.perf_counter() - tk)
             if k == 0:
-                e_fp64_first = float(e.item()) + shift
-        torch.cuda.synchronize()
-        t_fp64 = (time.perf_counter() - t0) / args.fp64_steps
-        e_fp64 = e_fp64_first
-        print(f"# fp64 sweep: {t_fp64:.3f} s/sweep, e = {e_fp64:.12f}", file=sys.stderr, flush=True)
-        del m64
+                e_one = e
+        recs_ = _lib.mera_profile_end()[1] if profile else None
+        del mm
+        return times, e_one, recs_
+
+    # ---- plain FP64 sweeps from the same starting state, for the ratio (median) ----
+    t_fp64, e_fp64, fp64_each = None, None, []
+    if args.fp64_steps > 0:
+        fp64_each, e_fp64, _ = timed_from_start(args.fp64_steps, "fp64")
+        t_fp64 = float(np.median(fp64_each))
+        print(f"# fp64 sweeps: {fp64_each} s, e = {e_fp64:.12f}", file=sys.stderr, flush=True)
 
     # ---- the FP32-contraction form of the sweep from the same state (time and energy) ----
-    t_fp32 = None
-    e_fp32 = None
+    t_fp32, e_fp32 = None, None
     if args.fp32_steps > 0 and prec != "fp32":
-        m32 = sweep.GpuMera(start_state["layers"], start_state["si"], start_state["rho_star"])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.fp32_steps):
-            e, c = sweep.sweep(m32, h1, shift, args.iters, "fp32")
-            if k == 0:
-                e_fp32 = float(e.item()) + shift
-        torch.cuda.synchronize()
-        t_fp32 = (time.perf_counter() - t0) / args.fp32_steps
+        ts, e_fp32, _ = timed_from_start(args.fp32_steps, "fp32")
+        t_fp32 = float(np.median(ts))
         print(f"# fp32 sweep: {t_fp32:.3f} s/sweep, e = {e_fp32:.12f}", file=sys.stderr, flush=True)
-        del m32
+
+    # ---- fixed point in the benchmark precision, ascent and environments on FP32 MFMA ----
+    t_f32env, e_f32env, env_f32_sweep = None, None, None
+    if args.fp32_env_steps > 0 and envp != "fp32":
+        ts, e_f32env, recs_f = timed_from_start(args.fp32_env_steps, prec, "fp32", profile=True)
+        t_f32env = float(np.median(ts))
+        env_f32_sweep = env_rates(recs_f, ops.PRECISIONS["fp32"], ops, _lib, "fp32")
+        print(f"# fixed point {prec}, environments fp32: {t_f32env:.3f} s/sweep, e = {e_f32env:.12f}",
+              file=sys.stderr, flush=True)
 
     # ---- every contraction in the benchmark precision (environments included) ----
-    t_red = None
-    e_red = None
-    env = None
+    t_red, e_red, env = None, None, None
     if args.all_reduced_steps > 0 and envp != prec:
-        mr = sweep.GpuMera(start_state["layers"], start_state["si"], start_state["rho_star"])
-        _lib.mera_profile_begin()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.all_reduced_steps):
-            e, c = sweep.sweep(mr, h1, shift, args.iters, prec)
-            if k == 0:
-                e_red = float(e.item()) + shift
-        torch.cuda.synchronize()
-        t_red = (time.perf_counter() - t0) / args.all_reduced_steps
-        _, recs_red = _lib.mera_profile_end()
-        env = env_rates(recs_red, code, ops, _lib)
+        ts, e_red, recs_red = timed_from_start(args.all_reduced_steps, prec, profile=True)
+        t_red = float(np.median(ts))
+        env = env_rates(recs_red, code, ops, _lib, prec)
         print(f"# all contractions {prec}: {t_red:.3f} s/sweep, e = {e_red:.12f}", file=sys.stderr, flush=True)
-        del mr
     else:
-        env = env_rates(recs, code, ops, _lib)
+        env = env_rates(recs, code, ops, _lib, prec)
+
+    # ---- evaluation parity at chi = 24 against the FP64 oracle (seeded state) ----
+    oracle_eval = evaluation_vs_oracle(args, h1, shift, sweep, prec)
+    if oracle_eval is not None:
+        print(f"# chi={chi} evaluation vs oracle: {oracle_eval}", file=sys.stderr, flush=True)
 
     # ---- energy evaluation at the final tensors: mixed pipeline vs FP64 pipeline ----
     def eval_energy(precision):
@@ -363,9 +434,9 @@ def main():
     cpu = None
     scan = None
     if args.cpu_baseline:
-        cpu = cpu_baseline(chi, args.seed)
+        cpu = cpu_baseline(chi, args.seed, sweep.layer_dims(m), args.iters)
         print(f"# cpu baseline: {cpu}", file=sys.stderr, flush=True)
-        scan = cpu_thread_scan(16, args.seed)
+        scan = cpu_thread_scan(chi, args.seed)
         print(f"# oracle thread scan: {scan}", file=sys.stderr, flush=True)
 
     value = flops["total"] / t_mixed / 1e12
@@ -401,7 +472,14 @@ def main():
         "sweep_s_mixed_median": round(float(np.median(each)), 4),
         "sweep_s_mixed_min": round(min(each), 4),
         "sweep_s_fp64": round(t_fp64, 4) if t_fp64 else None,
-        "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3) if t_fp64 else None,
+        "sweep_s_fp64_each": [round(x, 4) for x in fp64_each],
+        "speedup_mixed_vs_fp64": round(t_fp64 / float(np.median(each)), 3) if t_fp64 else None,
+        "speedup_note": "median FP64 sweep / median mixed sweep, same starting state",
+        "sweep_s_fp32_environments": round(t_f32env, 4) if t_f32env else None,
+        "speedup_fp32_environments_vs_fp64": round(t_fp64 / t_f32env, 3) if (t_f32env and t_fp64) else None,
+        "dE_one_sweep_fp32_environments_vs_fp64": abs(e_f32env - e_fp64) if (e_f32env is not None and e_fp64 is not None) else None,
+        "env_contraction_fp32_in_sweep": env_f32_sweep,
+        "evaluation_vs_oracle_chi24": oracle_eval,
         "sweep_s_all_contractions_reduced": round(t_red, 4) if t_red else None,
         "speedup_all_reduced_vs_fp64": round(t_fp64 / t_red, 3) if (t_red and t_fp64) else None,
         "dE_one_sweep_all_reduced_vs_fp64": abs(e_red - e_fp64) if (e_red is not None and e_fp64 is not None) else None,

@@ -94,10 +94,14 @@ def _as_matrix(x):
 
 
 def tangent_project(x, g):
-    """Project an ambient gradient onto the tangent space of {X : X^T X = I} at x."""
-    xm, gm = _as_matrix(x), _as_matrix(g)
-    s = xm.t() @ gm
-    return (gm - xm @ (0.5 * (s + s.t()))).reshape(x.shape)
+    """Project an ambient gradient onto the tangent space of {X : X^T X = I} at x:
+    G - X sym(X^T G), with the products on the library's contraction engine (FP64)."""
+    xm, gm = _as_matrix(x).contiguous(), _as_matrix(g).contiguous()
+    sym = ops.contract("ab,ac->bc", xm, gm, alpha=0.5)                 # (X^T G) / 2
+    ops.contract("ab,ac->bc", gm, xm, alpha=0.5, beta=1.0, out=sym)    # + (G^T X) / 2
+    out = gm.clone()
+    ops.contract("ab,bc->ac", xm, sym, alpha=-1.0, beta=1.0, out=out)  # G - X sym
+    return out.reshape(x.shape)
 
 
 def retract(x, step):

@@ -26,7 +26,7 @@ import time
 import numpy as np
 import torch
 
-from . import inputs, ops, scaling, sweep
+from . import autograd, inputs, ops, scaling, sweep
 
 EXACT = -4.0 / math.pi
 
@@ -48,21 +48,11 @@ def load_state(path, device="cuda"):
     return sweep.GpuMera(layers, (z["si_u"], z["si_w"]), z["rho_star"], device), meta
 
 
-def _project(mat):
-    q, r = np.linalg.qr(mat)
-    return q * np.sign(np.where(np.diag(r) == 0, 1.0, np.diag(r)))[None, :]
-
-
-def _polar(mat):
-    uu, _, vt = np.linalg.svd(mat, full_matrices=False)
-    return uu @ vt
-
-
-def grow(small_layers, small_si, chi, n_transitional, seed, noise=1e-3):
-    """Pad a smaller state to bond dimension chi: zero-pad legs, add seeded noise, re-project.
-
-    Layers beyond the small state's depth copy the small state's scale-invariant tensors.
-    """
+def pad_with_noise(small_layers, small_si, chi, n_transitional, seed, noise=1e-3):
+    """Warm-start input for a larger bond dimension chi (host; seeded random numbers only):
+    every leg of the smaller state's tensors zero-padded to the new dimensions, plus seeded
+    N(0, noise^2) entries.  Layers beyond the small state's depth start from its
+    scale-invariant tensors.  Returns (layers, si) before the projection onto isometries."""
     rng = np.random.default_rng(seed)
     dims = inputs.bond_dims(chi, n_transitional)
     src = list(small_layers) + [small_si] * (n_transitional - len(small_layers))
@@ -78,10 +68,25 @@ def grow(small_layers, small_si, chi, n_transitional, seed, noise=1e-3):
         w[:a, :a, :b] = w0[:a, :a, :b]
         u += noise * rng.standard_normal(u.shape)
         w += noise * rng.standard_normal(w.shape)
-        u = _polar(u.reshape(din * din, din * din)).reshape(u.shape)
-        w = _polar(w.reshape(din * din, dout)).reshape(w.shape)
         out.append((u, w))
     return out[:-1], out[-1]
+
+
+def grow(small_layers, small_si, chi, n_transitional, seed, noise=1e-3, device="cuda"):
+    """Pad a smaller state to bond dimension chi (pad_with_noise), then replace every tensor
+    by the nearest isometry, U V^T of its SVD, with the library's polar update on the GPU."""
+    layers, si = pad_with_noise(small_layers, small_si, chi, n_transitional, seed, noise)
+
+    def nearest_isometry(x, rows, cols):
+        y = torch.from_numpy(np.ascontiguousarray(x)).to(device)
+        out, _, _ = ops.polar_update(-y, rows, cols)  # -polar(-y) = +U V^T of y
+        return out.cpu().numpy()
+
+    def proj(u, w):
+        din, dout = w.shape[0], w.shape[2]
+        return (nearest_isometry(u, din * din, din * din), nearest_isometry(w, din * din, dout))
+
+    return [proj(u, w) for u, w in layers], proj(*si)
 
 
 def main(argv=None):
@@ -109,9 +114,19 @@ def main(argv=None):
                          "iterations), energy and (with --dims) scaling dimensions in each precision; "
                          "for --compare-sweeps an entry a/b runs the fixed point in a and the "
                          "environments in b")
+    ap.add_argument("--compare-riemannian", type=int, default=0,
+                    help="instead of optimising: this many SVD-update sweeps and this many Riemannian "
+                         "gradient steps (step --lr) from the same seeded state, energy after each")
+    ap.add_argument("--lr", type=float, default=0.02)
     a = ap.parse_args(argv)
     if not torch.cuda.is_available():
         raise SystemExit("a GPU is required")
+    if a.compare_riemannian > 0:
+        res = compare_riemannian(a.chi, a.layers, a.seed, a.compare_riemannian, a.lr, a.iters)
+        for method, es in res.items():
+            print(json.dumps({"method": method, "chi": a.chi, "lr": a.lr if method == "riemannian" else None,
+                              "energy": es, "rel_error": [(e - EXACT) / abs(EXACT) for e in es]}), flush=True)
+        return res
     start = 0
     if a.resume:
         m, meta = load_state(a.resume)
@@ -151,6 +166,31 @@ def main(argv=None):
     if a.compare_precisions:
         compare_precisions(m, h1, shift, a.compare_precisions.split(","), a.iters, a.dims, a.compare_sweeps)
     return e
+
+
+def compare_riemannian(chi, n_transitional, seed, nsteps, lr=0.02, iters=30):
+    """Energy per step of the SVD update (Sec. II.C, Fig. 5) and of Riemannian gradient
+    descent with the autograd environments (appendix, Fig. A1 caption) from the same seeded
+    state, FP64.  One SVD step is a sweep; one Riemannian step moves every tensor along its
+    projected gradient by lr and retracts with the polar update, then refreshes rho* with
+    `iters` power iterations.  Returns {"svd": [...], "riemannian": [...]}."""
+    h1, shift = ops.tfim_hamiltonian(1.0)
+    out = {}
+    for method in ("svd", "riemannian"):
+        m = sweep.GpuMera.seeded(chi, n_transitional, seed)
+        sweep.initial_fixed_point(m, iters, "fp64")
+        es = []
+        for _ in range(nsteps):
+            if method == "svd":
+                e, c = sweep.sweep(m, h1, shift, iters, "fp64")
+                es.append(float(e.item()) + c)
+            else:
+                autograd.riemannian_descent_step(m, h1, lr=lr)
+                sweep.initial_fixed_point(m, iters, "fp64")
+                es.append(sweep.energy(m, h1, shift))
+        out[method] = es
+        del m
+    return out
 
 
 def _copy(m):

@@ -116,6 +116,47 @@ def test_riemannian_step_lowers_energy(mods):
             assert torch.abs(xm.t() @ xm - eye).max() < 1e-12
 
 
+def test_autograd_gradients_chi12_are_twice_the_oracle_environments(mods):
+    """The differentiation form's configuration (chi = 12, three transitional layers, FP64):
+    the backward of the autograd energy against twice the oracle environments of every
+    transitional layer (appendix, Fig. A1 caption)."""
+    ops, sweep, autograd, _ = mods
+    say("autograd vs oracle environments chi=12 T=3")
+    layers, si, m = _state(12, 3, 0, sweep, ops, iters=30)
+    h1, _ = ops.tfim_hamiltonian(1.0)
+    pairs = [(u.clone().requires_grad_(True), w.clone().requires_grad_(True)) for u, w in m.layers]
+    e = autograd.energy(pairs, h1, m.rho_star)
+    e.backward()
+    rho_top = m.rho_star.cpu().numpy()
+    h_np, _ = O.shifted_hamiltonian()
+    st = O.MeraState(layers, si, rho_top)
+    hs = O.ascend_chain(st, h_np)
+    rhos = O.descend_chain(st, rho_top)
+    assert abs(float(e.detach()) - O.trace_product(h_np, rhos[0])) < 1e-12
+    for t, (u, w) in enumerate(pairs):
+        uo, wo = layers[t]
+        ref_u = 2 * O.env_u(uo, wo, hs[t], rhos[t + 1])
+        ref_w = 2 * O.env_w(uo, wo, hs[t], rhos[t + 1])
+        eu = np.abs(u.grad.cpu().numpy() - ref_u).max() / (1 + np.abs(ref_u).max())
+        ew = np.abs(w.grad.cpu().numpy() - ref_w).max() / (1 + np.abs(ref_w).max())
+        say(f"  layer {t}: max grad error u {eu:.2e} w {ew:.2e}")
+        assert eu < 1e-12 and ew < 1e-12
+
+
+def test_riemannian_descent_against_svd_update_chi12(mods):
+    """Same seeded chi = 12 state, same number of steps: both lower the energy and stay
+    variational; the SVD update, which jumps to the minimiser of the linearised energy, ends
+    lower than first-order Riemannian steps."""
+    from paper_1906_12030_amd import run
+    say("riemannian vs svd chi=12")
+    res = run.compare_riemannian(12, 3, 0, 12, lr=0.02, iters=30)
+    for k, es in res.items():
+        say(f"  {k}: " + " ".join(f"{e:.6f}" for e in es))
+        assert es[-1] < es[0], k
+        assert min(es) > -4 / np.pi
+    assert res["svd"][-1] < res["riemannian"][-1]
+
+
 def _golden():
     if not os.path.exists(GOLDEN):
         pytest.skip("golden state missing")

@@ -1,21 +1,52 @@
-"""Warm start by padding a smaller state (host-side numpy; no GPU needed)."""
+"""Warm start by padding a smaller state: host-side padding (no GPU) and the projection onto
+isometries by the library's polar update (GPU)."""
 import numpy as np
+import pytest
 
 from paper_1906_12030_amd import inputs as I
-from paper_1906_12030_amd.run import grow
+from paper_1906_12030_amd.run import grow, pad_with_noise
 
 
+def _dims(t, dims, T):
+    din = dims[t] if t < T else dims[-1]
+    dout = dims[t + 1] if t < T else dims[-1]
+    return din, dout
+
+
+def test_padding_keeps_the_small_tensors_and_adds_small_noise():
+    layers, si = I.init_mera(4, 2, 0)
+    new_layers, new_si = pad_with_noise(layers, si, 8, 3, seed=1)
+    dims = I.bond_dims(8, 3)
+    src = list(layers) + [si]
+    for t, (u, w) in enumerate(new_layers + [new_si]):
+        din, dout = _dims(t, dims, 3)
+        assert u.shape == (din,) * 4 and w.shape == (din, din, dout)
+        u0, w0 = src[min(t, 2)] if t < 3 else si
+        a, b = min(din, u0.shape[0]), min(dout, w0.shape[2])
+        assert np.abs(u[:a, :a, :a, :a] - u0[:a, :a, :a, :a]).max() < 6e-3
+        assert np.abs(w[:a, :a, :b] - w0[:a, :a, :b]).max() < 6e-3
+        assert 0.5e-3 < np.std(w[a:]) < 2e-3 if a < din else True
+
+
+@pytest.mark.gpu
 def test_grown_tensors_are_isometries_with_the_new_dimensions():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
     layers, si = I.init_mera(4, 2, 0)
     new_layers, new_si = grow(layers, si, 8, 3, seed=1)
+    padded, padded_si = pad_with_noise(layers, si, 8, 3, seed=1)
     dims = I.bond_dims(8, 3)
-    for t, (u, w) in enumerate(new_layers + [new_si]):
-        din = dims[t] if t < 3 else dims[-1]
-        dout = dims[t + 1] if t < 3 else dims[-1]
+    for t, ((u, w), (pu, pw)) in enumerate(zip(new_layers + [new_si], padded + [padded_si])):
+        din, dout = _dims(t, dims, 3)
         assert u.shape == (din,) * 4 and w.shape == (din, din, dout)
         um = u.reshape(din * din, din * din)
         wm = w.reshape(din * din, dout)
         assert np.abs(um.T @ um - np.eye(din * din)).max() < 1e-12
         assert np.abs(wm.T @ wm - np.eye(dout)).max() < 1e-12
+        # the nearest isometry: U V^T of the padded tensor's SVD (LAPACK as the comparator)
+        for x, y, rows, cols in ((um, pu, din * din, din * din), (wm, pw, din * din, dout)):
+            uu, _, vt = np.linalg.svd(y.reshape(rows, cols), full_matrices=False)
+            assert np.abs(x - uu @ vt).max() < 1e-8
     # the first transitional layer keeps its shape and stays close to the original
     assert np.abs(new_layers[0][1] - layers[0][1]).max() < 1e-2
