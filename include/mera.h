@@ -87,6 +87,25 @@ typedef struct {
   const double* w_d;
 } mera_layer;
 
+/* Allocation-free descend, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Computes exactly what mera_descend computes, with the same
+ * kernels, but takes its workspace from a static device array of
+ * MERA_NOALLOC_SCRATCH_MIB MiB inside the library instead of a caller buffer;
+ * every device the library runs on holds that array until the process ends.
+ * The chi^7 intermediates are sliced over an open leg until they fit; calls that
+ * need more than the array even then (for din = dout = chi: chi >= 14 in FP64,
+ * chi >= 15 in FP32 and split bf16) return MERA_EWORKSPACE before any HIP call.  hip_stream must belong to
+ * the calling thread's current device.  The call allocates nothing and keeps no
+ * result in the array that a later call depends on (every buffer taken from it
+ * is written before it is read), but all calls on one device share the array:
+ * calls that overlap in time on one device (several streams or host threads)
+ * race and must be serialised by the caller.  Per-launch profiling records are
+ * not taken for this call.  Asynchronous. */
+#define MERA_NOALLOC_SCRATCH_MIB 256
+int mera_descend_noalloc(const mera_layer* layer, const double* rho_in_d, double* rho_out_d,
+                         int placement, int precision, void* hip_stream);
+
 /* Ascending superoperator (Sec. II.B, Fig. 4a): h_out = A_P(h_in).
  * h_in_d: din^6 operator on the fine window; h_out_d: dout^6 operator on the
  * coarse window.  A_P is the adjoint of D_P: tr(A_P(o) rho) = tr(o D_P(rho)). */

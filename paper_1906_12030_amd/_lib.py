@@ -23,6 +23,7 @@ EXPORTED = (
     "mera_fixed_point_rho", "mera_energy", "mera_tfim_hamiltonian", "mera_workspace_bytes",
     "mera_strerror", "mera_last_error", "mera_flops", "mera_profile_begin", "mera_profile_end",
     "mera_workspace_bytes_min", "mera_mfma_peak", "mera_contract", "mera_schedule_plan",
+    "mera_descend_noalloc",
 )
 
 
@@ -57,6 +58,8 @@ def load() -> ctypes.CDLL:
     lp = ctypes.POINTER(MeraLayer)
     lib.mera_ascend.argtypes = [lp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
     lib.mera_descend.argtypes = [lp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
+    lib.mera_descend_noalloc.argtypes = [lp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.mera_descend_noalloc.restype = ctypes.c_int
     lib.mera_env_u.argtypes = [lp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
     lib.mera_env_w.argtypes = [lp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
     lib.mera_polar_update.argtypes = [vp, i64, i64, vp, vp, vp, sz, vp]
@@ -98,6 +101,10 @@ def check(status: int, where: str) -> None:
         detail = lib.mera_strerror(status).decode()
         last = lib.mera_last_error().decode()
         raise MeraError(status, where, f"{detail} ({last})" if last else detail)
+
+
+def mera_descend_noalloc(layer, rho_in_d, rho_out_d, placement, precision, stream):
+    return load().mera_descend_noalloc(ctypes.byref(layer), rho_in_d, rho_out_d, placement, precision, stream)
 
 
 def mera_ascend(layer, h_in_d, h_out_d, placement, precision, ws_d, ws_bytes, stream):

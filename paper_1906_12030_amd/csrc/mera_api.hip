@@ -31,11 +31,18 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/mera.h"
 #include "engine.h"
+
+// Workspace of mera_descend_noalloc: a static device array that every device
+// the library runs on holds until the process ends.  In host code `scratch`
+// is only a handle for hipGetSymbolAddress, never a device address.
+constexpr size_t kNoAllocScratchBytes = size_t(MERA_NOALLOC_SCRATCH_MIB) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace {
 
@@ -508,6 +515,40 @@ int check_enum(int placement, int precision) {
   return MERA_OK;
 }
 
+// Device address of `scratch` on the calling thread's current device, looked up
+// with that device current on the first call there and kept per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    set_err(std::string("no usable current device: ") + hipGetErrorString(e));
+    return MERA_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_err(std::string("static scratch address: ") + hipGetErrorString(e));
+      return MERA_EDEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MERA_OK;
+}
+
+// Turns per-launch profiling records (which create HIP events) off for a scope.
+struct NoProfile {
+  bool prev;
+  NoProfile() : prev(g_prof_on) { g_prof_on = false; }
+  ~NoProfile() { g_prof_on = prev; }
+};
+
 Arith arith_of(int precision) {
   return precision == MERA_FP64 ? Arith::F64 : precision == MERA_FP32 ? Arith::F32 : Arith::B3;
 }
@@ -831,6 +872,33 @@ int mera_descend(const mera_layer* layer, const double* rho_in_d, double* rho_ou
     return MERA_EWORKSPACE;
   }
   return run_checked(cx, ws_d, ws_bytes, hip_stream,
+                     [&](Ctx& c) { run_descend(c, layer, rho_in_d, rho_out_d, placement, S); });
+}
+
+int mera_descend_noalloc(const mera_layer* layer, const double* rho_in_d, double* rho_out_d,
+                         int placement, int precision, void* hip_stream) {
+  OpTag tag(MERA_OP_DESCEND);
+  int st = check_layer(layer);
+  if (st) return st;
+  if ((st = check_enum(placement, precision))) return st;
+  if (!rho_in_d || !rho_out_d) {
+    set_err("null tensor pointer");
+    return MERA_EINVAL;
+  }
+  Ctx cx;
+  cx.ar = arith_of(precision);
+  const int S = choose_slices(cx, layer->din, kNoAllocScratchBytes, [&](Ctx& c, int s) {
+    run_descend(c, layer, rho_in_d, rho_out_d, placement, s);
+  });
+  if (S == 0) {
+    set_err("descend needs more than the static scratch (" + std::to_string(MERA_NOALLOC_SCRATCH_MIB) +
+            " MiB) even with the chi^7 intermediates sliced");
+    return MERA_EWORKSPACE;
+  }
+  void* ws = nullptr;
+  if ((st = scratch_of_current_device(&ws))) return st;
+  NoProfile quiet;
+  return run_checked(cx, ws, kNoAllocScratchBytes, hip_stream,
                      [&](Ctx& c) { run_descend(c, layer, rho_in_d, rho_out_d, placement, S); });
 }
 

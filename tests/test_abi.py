@@ -67,6 +67,23 @@ def test_invalid_arguments_rejected_before_device(lib):
     assert lib.mera_last_error()
 
 
+def test_noalloc_descend_rejects_what_the_static_scratch_cannot_hold(lib):
+    fake = 4096  # never dereferenced: the size check fails before any HIP call
+    for d, prec in ((14, 0), (15, 1), (15, 2), (24, 2)):
+        assert _lib.mera_descend_noalloc(_layer(d, d), fake, fake, 2, prec, None) == _lib.MERA_EWORKSPACE
+        assert b"static scratch" in lib.mera_last_error()
+    assert _lib.mera_descend_noalloc(_layer(4, 17), fake, fake, 2, 0, None) == _lib.MERA_ESHAPE
+    assert _lib.mera_descend_noalloc(_layer(4, 4), None, fake, 2, 0, None) == _lib.MERA_EINVAL
+    assert _lib.mera_descend_noalloc(_layer(4, 4), fake, fake, 5, 0, None) == _lib.MERA_EINVAL
+    # the limit in the header is the one the library applies
+    mib = int(re.search(r"#define MERA_NOALLOC_SCRATCH_MIB (\d+)",
+                        open(os.path.join(ROOT, "include", "mera.h")).read()).group(1))
+    for d in (13, 14):
+        for prec in (0, 1, 2):
+            fits = _lib.mera_workspace_bytes_min(_lib.MERA_OP_DESCEND, d, d, prec, 2) <= mib << 20
+            assert fits == (d == 13 or prec != 0), (d, prec)
+
+
 def test_workspace_too_small_and_misaligned(lib):
     fake = 4096
     need = _lib.mera_workspace_bytes(_lib.MERA_OP_DESCEND, 4, 4, 0, 2)
