@@ -16,9 +16,14 @@
 //     with one barrier per k-tile: the loads of tile kt+1 fly while the
 //     MFMAs of tile kt run, and no registers are spent on staging;
 //   * LDS rows are 128 bytes (eight 16-byte slots of 4 k each); slot s of
-//     row r is stored at s ^ swz(r) so that the fragment reads of a
-//     half-wave (16 rows x 2 slots) hit 32 distinct 16-byte slots modulo
-//     512 bytes (conflict-free on gfx950's LDS);
+//     row r is stored at s ^ swz(r), swz(r) = (r & 7) ^ ((r >> 3) & 1), so
+//     that in every fragment read (lane l: row l % 16, slot 2 (l / 16) + h)
+//     each group of 8 consecutive lanes hits 8 distinct 16-byte slots modulo
+//     128 bytes, each group of 16 lanes 16 distinct slots modulo 256 bytes and
+//     each group of 32 lanes 32 distinct slots modulo 512 bytes: no bank
+//     conflict whichever of these lane groups the LDS serves per cycle (the
+//     LDS bank-conflict counter showed 2-way conflicts with the previous
+//     swizzle, which only met the last condition);
 //   * each lane reads its 8 consecutive k of a row as two 16-byte slots
 //     and regroups the halves into the hi and lo MFMA operands (v_perm).
 #include <hip/hip_runtime.h>
@@ -39,8 +44,8 @@ constexpr int kBM = 256;
 constexpr int kBK = 32;
 constexpr int kRowBytes = kBK * 4;  // one row of a k-tile: 32 split words
 
-// slot swizzle: bits 2 and 3 of the row select bits 0 and 2 of the slot
-__device__ __forceinline__ int swz(int r) { return ((r >> 2) & 1) | (((r >> 3) & 1) << 2); }
+// slot swizzle: the row's low three bits, bit 0 flipped by row bit 3
+__device__ __forceinline__ int swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
 __device__ __forceinline__ uint32_t hi_pair(uint32_t a, uint32_t b) {
   return __builtin_amdgcn_perm(b, a, 0x07060302u);
