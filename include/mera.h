@@ -94,8 +94,10 @@ typedef struct {
  * MERA_NOALLOC_SCRATCH_MIB MiB inside the library instead of a caller buffer;
  * every device the library runs on holds that array until the process ends.
  * The chi^7 intermediates are sliced over an open leg until they fit; calls that
- * need more than the array even then (for din = dout = chi: chi >= 14 in FP64,
- * chi >= 15 in FP32 and split bf16) return MERA_EWORKSPACE before any HIP call.  hip_stream must belong to
+ * need more than the array even then (mera_workspace_bytes_min(MERA_OP_DESCEND,
+ * ...) above it; for din = dout = chi: chi >= 14 in FP64, chi >= 15 in FP32,
+ * chi = 13 and chi >= 15 in split bf16) return MERA_EWORKSPACE before any HIP
+ * call.  hip_stream must belong to
  * the calling thread's current device.  The call allocates nothing and keeps no
  * result in the array that a later call depends on (every buffer taken from it
  * is written before it is read), but all calls on one device share the array:

@@ -24,19 +24,34 @@ __global__ void k_to_f32(const double* __restrict__ x, float* __restrict__ y, in
     y[i] = (float)x[i];
 }
 
-__global__ void k_to_split(const double* __restrict__ x, uint32_t* __restrict__ y, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = pack_split((float)x[i]);
+// Split tensor of (float) x: one thread per 32-byte group of 8 elements (the
+// padding of a last, partial group is written as zeros).
+__global__ void k_to_split(const double* __restrict__ x, uint16_t* __restrict__ y, int64_t n) {
+  typedef uint16_t h8_t __attribute__((ext_vector_type(8)));
+  const int64_t groups = (n + 7) >> 3;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < groups;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    h8_t h, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t i = 8 * g + e;
+      const float v = i < n ? (float)x[i] : 0.f;
+      h[e] = bf16_bits(v);
+      l[e] = bf16_bits(v - bf16_value(h[e]));
+    }
+    *reinterpret_cast<h8_t*>(y + 16 * g) = h;
+    *reinterpret_cast<h8_t*>(y + 16 * g + 8) = l;
+  }
 }
 
-// Split words of a d^6 density x[i j k I J K] written as y[j k J K i I]: a
+// Split tensor of a d^6 density x[i j k I J K] written as y[j k J K i I]: a
 // transpose of the d^2 x d^4 matrix (rows (i, I), columns (j, k, J, K)) in
 // 64 x 64 tiles through LDS, so that the loads run along the columns (the
 // innermost J K of x) and the stores along the rows (the innermost i I of y).
+// The padding of a last, partial group (d odd) is never read.
 __global__ __launch_bounds__(256) void k_rho_to_split_perm(const double* __restrict__ x,
-                                                           uint32_t* __restrict__ y, int32_t d) {
-  __shared__ uint32_t t[64][65];
+                                                           uint16_t* __restrict__ y, int32_t d) {
+  __shared__ float t[64][65];
   const int64_t d2 = (int64_t)d * d, d3 = d2 * d, d4 = d3 * d, d5 = d4 * d;
   const int64_t c0 = (int64_t)blockIdx.x * 64;
   const int64_t r0 = (int64_t)blockIdx.y * 64;
@@ -48,7 +63,7 @@ __global__ __launch_bounds__(256) void k_rho_to_split_perm(const double* __restr
     for (int q = 0; q < 16; ++q) {
       const int rl = ty + 4 * q;
       const int64_t r = r0 + rl;
-      if (r < d2) t[rl][tx] = pack_split((float)x[(r / d) * d5 + (r % d) * d2 + coff]);
+      if (r < d2) t[rl][tx] = (float)x[(r / d) * d5 + (r % d) * d2 + coff];
     }
   }
   __syncthreads();
@@ -58,7 +73,7 @@ __global__ __launch_bounds__(256) void k_rho_to_split_perm(const double* __restr
     for (int q = 0; q < 16; ++q) {
       const int cl = ty + 4 * q;
       const int64_t cc = c0 + cl;
-      if (cc < d4) y[cc * d2 + r] = t[tx][cl];
+      if (cc < d4) split_store(y, cc * d2 + r, t[tx][cl]);
     }
   }
 }
@@ -193,8 +208,8 @@ hipError_t launch_sqrt_ratio(const double* a, const double* b, double* out, hipS
 
 hipError_t launch_to_f32(const double* x, float* y, int64_t n, bool split, hipStream_t s) {
   if (split)
-    hipLaunchKernelGGL(k_to_split, dim3(grid_for(n)), dim3(kBlock), 0, s, x,
-                       reinterpret_cast<uint32_t*>(y), n);
+    hipLaunchKernelGGL(k_to_split, dim3(grid_for((n + 7) / 8, 1)), dim3(kBlock), 0, s, x,
+                       reinterpret_cast<uint16_t*>(y), n);
   else
     hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
   return hipGetLastError();
@@ -202,7 +217,7 @@ hipError_t launch_to_f32(const double* x, float* y, int64_t n, bool split, hipSt
 hipError_t launch_rho_to_split_perm(const double* x, float* y, int32_t d, hipStream_t s) {
   const int64_t d2 = (int64_t)d * d;
   const dim3 grid((unsigned)((d2 * d2 + 63) / 64), (unsigned)((d2 + 63) / 64));
-  hipLaunchKernelGGL(k_rho_to_split_perm, grid, dim3(256), 0, s, x, reinterpret_cast<uint32_t*>(y), d);
+  hipLaunchKernelGGL(k_rho_to_split_perm, grid, dim3(256), 0, s, x, reinterpret_cast<uint16_t*>(y), d);
   return hipGetLastError();
 }
 hipError_t launch_scale(const double* x, double* y, double a, int64_t n, hipStream_t s) {

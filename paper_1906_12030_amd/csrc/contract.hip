@@ -175,10 +175,11 @@ __global__ __launch_bounds__(256) void tc_splitk_reduce(TcArgs p) {
     double s = 0.0;
     for (int c = 0; c < p.splits; ++c) s += p.part[c * mn + t];
     const uint32_t m = (uint32_t)(t / p.N), n = (uint32_t)(t - (int64_t)m * p.N);
-    TC* dst = static_cast<TC*>(p.c) + goff<true>(p.gm, m) + goff<true>(p.gn, n);
+    TC* C = static_cast<TC*>(p.c);
+    const int64_t off = goff<true>(p.gm, m) + goff<true>(p.gn, n);
     double y = p.alpha * s;
-    if (p.beta != 0.0) y += p.beta * load_c(p, dst);
-    *dst = store_c<TC>(p, y);
+    if (p.beta != 0.0) y += p.beta * load_c(p, C, off);
+    store_c(p, C, off, y);
   }
 }
 
@@ -368,7 +369,7 @@ hipError_t make_plan(Arith ar, const LabelDims& dims, const LabelDims& cd, const
   args.K = (int32_t)K;
   args.alpha = alpha;
   args.beta = beta;
-  // the split-bf16 path keeps its FP32 intermediates as split words
+  // the split-bf16 path keeps its FP32 intermediates as split tensors
   args.csplit = (ar == Arith::B3 && !c_f64) ? 1 : 0;
   // loader modes: contiguous leg of A along k (else along m); of B along n (else along k)
   const bool akc = a_last_k && args.gk.sx[args.gk.nd - 1] == 1;

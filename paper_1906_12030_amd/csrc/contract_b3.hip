@@ -6,12 +6,13 @@
 //   hi_a*hi_b + hi_a*lo_b + lo_a*hi_b      (lo*lo, of relative size 2^-16, is dropped)
 // with FP32 accumulation (Henry, Tang and Heinecke, "Leveraging the bfloat16
 // artificial intelligence datatype for higher-precision computations",
-// ARITH 2019).  Operands and FP32 results are kept in HBM as split words
-// (hi in the upper, lo in the lower half of a 4-byte element; see
-// pack_split), so the split is done once, by the producer of a tensor, and
-// the loaders here only regroup halves: one v_perm per element on the way
-// into LDS.  The addressing (separable leg offsets, XCD-aware tile order) is
-// the same as in the FP64/FP32 kernel of contract.hip.
+// ARITH 2019).  Operands and FP32 results are kept in HBM as split tensors
+// (hi and lo halves of 8 consecutive elements in two 16-byte halves of a
+// 32-byte group; see split_hi in tc_common.h), so the split is done once, by
+// the producer of a tensor; the loaders here read hi and lo halves and place
+// them in the hi and lo slots of the LDS tile.  The addressing (separable leg
+// offsets, XCD-aware tile order) is the same as in the FP64/FP32 kernel of
+// contract.hip.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -28,12 +29,26 @@ typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u2_t __attribute__((ext_vector_type(2)));
 
-// hi (lo) halves of two consecutive-k split words, first word in the low half
-__device__ __forceinline__ uint32_t hi_pair(float a, float b) {
-  return __builtin_amdgcn_perm(__float_as_uint(b), __float_as_uint(a), 0x07060302u);
-}
-__device__ __forceinline__ uint32_t lo_pair(float a, float b) {
-  return __builtin_amdgcn_perm(__float_as_uint(b), __float_as_uint(a), 0x05040100u);
+typedef uint16_t h4_t __attribute__((ext_vector_type(4)));
+
+// hi and lo halves of element i of the split tensor at base (V = 1), or of
+// elements i .. i + 3 (V = 4, i a multiple of 4: one 8-byte load each)
+template <int V>
+__device__ __forceinline__ void load_halves(const uint16_t* __restrict__ base, int64_t i, uint16_t* hi,
+                                            uint16_t* lo) {
+  const uint16_t* q = base + split_hi(i);
+  if constexpr (V == 4) {
+    const h4_t h = *reinterpret_cast<const h4_t*>(q);
+    const h4_t l = *reinterpret_cast<const h4_t*>(q + 8);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      hi[v] = h[v];
+      lo[v] = l[v];
+    }
+  } else {
+    hi[0] = q[0];
+    lo[0] = q[8];
+  }
 }
 
 constexpr int kBM = 128;
@@ -57,28 +72,47 @@ __device__ __forceinline__ int swz(int r) { return (((r >> 2) & 3) << 1) | ((r >
 __device__ __forceinline__ int slot_off(int r, int s) { return r * kRowBytes + ((s ^ swz(r)) << 4); }
 
 // Operand loaders for the split kernel.  KC operands (contiguous along k)
-// use TileLoad (V consecutive k of one row per thread); operands contiguous
-// along their rows (m for A, n for B) are read 16 k per thread at one row, so
-// that every global load of a wave covers 64 consecutive rows and every LDS
-// write is a 16-byte slot.  The store regroups the split words' halves into
-// the hi and lo slots (one v_perm per element).
+// take TileLoad's geometry and offsets (V consecutive k of one row per
+// thread) and read the hi and lo halves of those elements; operands
+// contiguous along their rows (m for A, n for B) are read 16 k per thread at
+// one row, so that every global load of a wave covers 64 consecutive rows and
+// every LDS write is a 16-byte slot.
 template <bool KC, int V, bool KAL, bool KSecond>
 struct B3Load;
 
 template <int V, bool KAL, bool KSecond>
 struct B3Load<true, V, KAL, KSecond> {
-  using TL = TileLoad<float, 128, kBK, true, V, KAL, KSecond>;
+  using TL = TileLoad<float, 128, kBK, true, V, KAL, KSecond>;  // geometry and offsets only
   TL t;
+  uint16_t h[TL::NP][V], l[TL::NP][V];
   __device__ __forceinline__ void init(const Group& grow, const Group& gk, uint32_t row0,
                                        uint32_t nrows) {
     t.init(grow, gk, row0, nrows);
   }
   __device__ __forceinline__ void load_at(const float* __restrict__ base, int64_t kb) {
-    t.load_at(base, kb);
+    const uint16_t* b16 = reinterpret_cast<const uint16_t*>(base);
+#pragma unroll
+    for (int i = 0; i < TL::NP; ++i) load_halves<V>(b16, t.roff[i] + kb + t.kd[0], h[i], l[i]);
   }
   __device__ __forceinline__ void load(const float* __restrict__ base, const Group& gk, uint32_t k0,
                                        uint32_t kend) {
-    t.load(base, gk, k0, kend);
+    if constexpr (KAL) {
+      load_at(base, goff<KSecond>(gk, k0));
+    } else {
+      const uint16_t* b16 = reinterpret_cast<const uint16_t*>(base);
+      const uint32_t k = k0 + t.vec;
+      const bool kok = k < kend;
+      const int64_t ko = kok ? goff<KSecond>(gk, k) : 0;
+#pragma unroll
+      for (int i = 0; i < TL::NP; ++i) {
+        if (kok && t.rok[i]) {
+          load_halves<V>(b16, t.roff[i] + ko, h[i], l[i]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) h[i][v] = l[i][v] = 0;
+        }
+      }
+    }
   }
   __device__ __forceinline__ void store(char* T) {
     const int s = t.vec >> 3;       // k-slot of this thread's k
@@ -89,22 +123,17 @@ struct B3Load<true, V, KAL, KSecond> {
 #pragma unroll
     for (int i = 0; i < TL::NP; ++i) {
       const int r = t.line + i * TL::LPP;
-      const float* x = t.r[i];
-      if constexpr (V == 4 && TL::LPP % 32 == 0) {
-        *reinterpret_cast<u2_t*>(T + oh + i * TL::LPP * kRowBytes) =
-            u2_t{hi_pair(x[0], x[1]), hi_pair(x[2], x[3])};
-        *reinterpret_cast<u2_t*>(T + ol + i * TL::LPP * kRowBytes) =
-            u2_t{lo_pair(x[0], x[1]), lo_pair(x[2], x[3])};
-      } else if constexpr (V == 4) {
-        *reinterpret_cast<u2_t*>(T + slot_off(r, s) + b) = u2_t{hi_pair(x[0], x[1]), hi_pair(x[2], x[3])};
-        *reinterpret_cast<u2_t*>(T + slot_off(r, 4 + s) + b) =
-            u2_t{lo_pair(x[0], x[1]), lo_pair(x[2], x[3])};
+      if constexpr (V == 4) {
+        const int o = TL::LPP % 32 == 0 ? i * TL::LPP * kRowBytes : 0;
+        const int ph = TL::LPP % 32 == 0 ? oh + o : slot_off(r, s) + b;
+        const int pl = TL::LPP % 32 == 0 ? ol + o : slot_off(r, 4 + s) + b;
+        *reinterpret_cast<h4_t*>(T + ph) = h4_t{h[i][0], h[i][1], h[i][2], h[i][3]};
+        *reinterpret_cast<h4_t*>(T + pl) = h4_t{l[i][0], l[i][1], l[i][2], l[i][3]};
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          const uint32_t w = __float_as_uint(x[v]);
-          *reinterpret_cast<uint16_t*>(T + slot_off(r, s) + b + 2 * v) = (uint16_t)(w >> 16);
-          *reinterpret_cast<uint16_t*>(T + slot_off(r, 4 + s) + b + 2 * v) = (uint16_t)(w & 0xffffu);
+          *reinterpret_cast<uint16_t*>(T + slot_off(r, s) + b + 2 * v) = h[i][v];
+          *reinterpret_cast<uint16_t*>(T + slot_off(r, 4 + s) + b + 2 * v) = l[i][v];
         }
       }
     }
@@ -116,7 +145,7 @@ struct B3Load<false, V, KAL, KSecond> {
   static_assert(kThreads == 2 * 128 && kBK == 32, "row loader geometry");
   int row, kg;
   int64_t roff, ks;
-  float r[16];
+  uint16_t h[16], l[16];
   __device__ __forceinline__ void init(const Group& grow, const Group& gk, uint32_t row0,
                                        uint32_t nrows) {
     row = threadIdx.x & 127;
@@ -127,26 +156,32 @@ struct B3Load<false, V, KAL, KSecond> {
     ks = KSecond ? gk.sy[gk.nd - 1] : gk.sx[gk.nd - 1];
   }
   __device__ __forceinline__ void load_at(const float* __restrict__ base, int64_t kb) {
-    const float* q = base + roff + kb + (int64_t)(kg * 16) * ks;
+    const uint16_t* b16 = reinterpret_cast<const uint16_t*>(base);
+    const int64_t q = roff + kb + (int64_t)(kg * 16) * ks;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) r[e] = q[(int64_t)e * ks];
+    for (int e = 0; e < 16; ++e) load_halves<1>(b16, q + (int64_t)e * ks, &h[e], &l[e]);
   }
   __device__ __forceinline__ void load(const float* __restrict__ base, const Group& gk, uint32_t k0,
                                        uint32_t kend) {
+    const uint16_t* b16 = reinterpret_cast<const uint16_t*>(base);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const uint32_t k = k0 + kg * 16 + e;
-      r[e] = k < kend ? base[roff + goff<KSecond>(gk, k)] : 0.f;
+      if (k < kend) {
+        load_halves<1>(b16, roff + goff<KSecond>(gk, k), &h[e], &l[e]);
+      } else {
+        h[e] = l[e] = 0;
+      }
     }
   }
   __device__ __forceinline__ void store(char* T) {
     u4_t h0, h1, l0, l1;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      h0[e] = hi_pair(r[2 * e], r[2 * e + 1]);
-      l0[e] = lo_pair(r[2 * e], r[2 * e + 1]);
-      h1[e] = hi_pair(r[8 + 2 * e], r[8 + 2 * e + 1]);
-      l1[e] = lo_pair(r[8 + 2 * e], r[8 + 2 * e + 1]);
+      h0[e] = (uint32_t)h[2 * e] | ((uint32_t)h[2 * e + 1] << 16);
+      l0[e] = (uint32_t)l[2 * e] | ((uint32_t)l[2 * e + 1] << 16);
+      h1[e] = (uint32_t)h[8 + 2 * e] | ((uint32_t)h[8 + 2 * e + 1] << 16);
+      l1[e] = (uint32_t)l[8 + 2 * e] | ((uint32_t)l[8 + 2 * e + 1] << 16);
     }
     *reinterpret_cast<u4_t*>(T + slot_off(row, 2 * kg)) = h0;
     *reinterpret_cast<u4_t*>(T + slot_off(row, 2 * kg + 1)) = h1;

@@ -1,7 +1,7 @@
 // Large-tile split-bf16 contraction kernel for gfx950 (operands contiguous
 // along k).
 //
-// Same arithmetic as contract_b3.hip (split words hi|lo, three BF16 MFMA
+// Same arithmetic as contract_b3.hip (split tensors, three BF16 MFMA
 // products per multiply-add, FP32 accumulation), organised for the long
 // chi^9 contractions whose k-tiles both operands store contiguously:
 //   * 256 x BN output tile, 512 threads = 8 waves on v_mfma_f32_16x16x32_bf16:
@@ -11,11 +11,12 @@
 //     A fragments held, B fragments streamed; 21 % fewer LDS bytes per flop
 //     than 256 x 192); twice the tile edge of the 128 x 128 kernel halves the
 //     bytes that have to come through L2 per flop;
-//   * operand k-tiles (32 split words per row) go straight from global
-//     memory into LDS with global_load_lds_dwordx4, in a two-stage ring
+//   * operand k-tiles (32 split elements, 128 bytes, per row) go straight
+//     from global memory into LDS with global_load_lds_dwordx4, in a two-stage ring
 //     with one barrier per k-tile: the loads of tile kt+1 fly while the
 //     MFMAs of tile kt run, and no registers are spent on staging;
-//   * LDS rows are 128 bytes (eight 16-byte slots of 4 k each); slot s of
+//   * LDS rows are 128 bytes (eight 16-byte slots: the hi, then the lo halves
+//     of k 0-7, then of k 8-15, ...); slot s of
 //     row r is stored at s ^ swz(r), swz(r) = (r & 7) ^ ((r >> 3) & 1), so
 //     that in every fragment read (lane l: row l % 16, slot 2 (l / 16) + h)
 //     each group of 8 consecutive lanes hits 8 distinct 16-byte slots modulo
@@ -24,8 +25,11 @@
 //     conflict whichever of these lane groups the LDS serves per cycle (the
 //     LDS bank-conflict counter showed 2-way conflicts with the previous
 //     swizzle, which only met the last condition);
-//   * each lane reads its 8 consecutive k of a row as two 16-byte slots
-//     and regroups the halves into the hi and lo MFMA operands (v_perm).
+//   * each lane reads its 8 consecutive k of a row as two 16-byte slots:
+//     in a split tensor these are the hi halves and the lo halves of the
+//     8 elements (see split_hi in tc_common.h), i.e. the two bf16x8 MFMA
+//     operands themselves, so no regrouping instruction sits between the
+//     LDS read and the MFMA.
 #include <hip/hip_runtime.h>
 
 #include "engine.h"
@@ -42,17 +46,11 @@ typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 constexpr int kThreadsX = 512;
 constexpr int kBM = 256;
 constexpr int kBK = 32;
-constexpr int kRowBytes = kBK * 4;  // one row of a k-tile: 32 split words
+constexpr int kRowBytes = kBK * 4;  // one row of a k-tile: 32 split elements
 
 // slot swizzle: the row's low three bits, bit 0 flipped by row bit 3
 __device__ __forceinline__ int swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
-__device__ __forceinline__ uint32_t hi_pair(uint32_t a, uint32_t b) {
-  return __builtin_amdgcn_perm(b, a, 0x07060302u);
-}
-__device__ __forceinline__ uint32_t lo_pair(uint32_t a, uint32_t b) {
-  return __builtin_amdgcn_perm(b, a, 0x05040100u);
-}
 
 // Workgroup barrier without the memory fence of __syncthreads(): that fence
 // would wait for every LDS-DMA load of the wave (vmcnt(0)), including the
@@ -146,30 +144,15 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[Geo<BN
         const int64_t co = cols[wn + j * 16 + (lane & 15)];
         if (co < 0) continue;
         if (mvec) {  // rows r0 .. r0 + 3 are all inside M (M % 4 == 0) and adjacent in C
-          TC* dst = C + rows[r0] + co;
-          TC out[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            double y = alpha * (double)acc[i][j][e];
-            if (beta != 0.0) y += beta * load_c(p, dst + e);
-            out[e] = store_c<TC>(p, y);
-          }
-          if constexpr (sizeof(TC) == 4) {
-            *reinterpret_cast<f4_t*>(dst) = f4_t{out[0], out[1], out[2], out[3]};
-          } else {
-            typedef double d2_t __attribute__((ext_vector_type(2)));
-            *reinterpret_cast<d2_t*>(dst) = d2_t{out[0], out[1]};
-            *reinterpret_cast<d2_t*>(dst + 2) = d2_t{out[2], out[3]};
-          }
+          store_c4(p, C, rows[r0] + co, acc[i][j], alpha, beta);
         } else {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int64_t re = rows[r0 + e];
             if (re < 0) continue;
-            TC* dst = C + re + co;
             double y = alpha * (double)acc[i][j][e];
-            if (beta != 0.0) y += beta * load_c(p, dst);
-            *dst = store_c<TC>(p, y);
+            if (beta != 0.0) y += beta * load_c(p, C, re + co);
+            store_c(p, C, re + co, y);
           }
         }
       }
@@ -204,30 +187,15 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[Geo<BN
       const f4_t x = *reinterpret_cast<const f4_t*>(&st[row * LD + col]);
       const int64_t co = cols[col];
       if (vec && co >= 0) {
-        TC* dst = C + ro + co;
-        TC out[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          double y = alpha * (double)x[e];
-          if (beta != 0.0) y += beta * load_c(p, dst + e);
-          out[e] = store_c<TC>(p, y);
-        }
-        if constexpr (sizeof(TC) == 4) {
-          *reinterpret_cast<f4_t*>(dst) = f4_t{out[0], out[1], out[2], out[3]};
-        } else {
-          typedef double d2_t __attribute__((ext_vector_type(2)));
-          *reinterpret_cast<d2_t*>(dst) = d2_t{out[0], out[1]};
-          *reinterpret_cast<d2_t*>(dst + 2) = d2_t{out[2], out[3]};
-        }
+        store_c4(p, C, ro + co, x, alpha, beta);
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int64_t ce = cols[col + e];
           if (ce < 0) continue;
-          TC* dst = C + ro + ce;
           double y = alpha * (double)x[e];
-          if (beta != 0.0) y += beta * load_c(p, dst);
-          *dst = store_c<TC>(p, y);
+          if (beta != 0.0) y += beta * load_c(p, C, ro + ce);
+          store_c(p, C, ro + ce, y);
         }
       }
     }
@@ -256,7 +224,9 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
 
   // DMA sources: chunk c (8 rows) of a tile is loaded by wave c % 8 as its
   // instruction c / 8; lane l fills physical slot l % 8 of row 8c + l / 8,
-  // i.e. logical slot (l % 8) ^ swz(row) = k 4*slot .. 4*slot+3.
+  // i.e. logical slot s = (l % 8) ^ swz(row): bytes 16 s .. 16 s + 15 of the
+  // row's 128-byte k-tile, the hi (s even) or lo (s odd) halves of elements
+  // k = 8 (s / 2) .. 8 (s / 2) + 7.
   int64_t asrc[G::kAIns], bsrc[G::kBIns];
   {
     const int rl = lane >> 3, ph = lane & 7;
@@ -299,16 +269,16 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
 #pragma unroll
     for (int j = 0; j < G::kWNB; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-  // fragment offsets: rows wm + 16 i + lr (wn + 16 j + lr), slots 2 kq and 2 kq + 1
+  // fragment offsets: rows wm + 16 i + lr (wn + 16 j + lr), slots 2 kq (hi) and
+  // 2 kq + 1 (lo) of k = 8 kq .. 8 kq + 7
   const int lr = lane & 15, kq = lane >> 4, sw = swz(lr);
   const int x0 = ((2 * kq) ^ sw) << 4, x1 = ((2 * kq + 1) ^ sw) << 4;
   const int abase = (wm + lr) * kRowBytes, bbase = (wn + lr) * kRowBytes;
 
+  // the two slots of a lane are the hi and the lo halves of its 8 elements
   auto split8 = [](const u4_t& w0, const u4_t& w1, bf8_t& hi, bf8_t& lo) {
-    const u4_t h = {hi_pair(w0.x, w0.y), hi_pair(w0.z, w0.w), hi_pair(w1.x, w1.y), hi_pair(w1.z, w1.w)};
-    const u4_t l = {lo_pair(w0.x, w0.y), lo_pair(w0.z, w0.w), lo_pair(w1.x, w1.y), lo_pair(w1.z, w1.w)};
-    hi = __builtin_bit_cast(bf8_t, h);
-    lo = __builtin_bit_cast(bf8_t, l);
+    hi = __builtin_bit_cast(bf8_t, w0);
+    lo = __builtin_bit_cast(bf8_t, w1);
   };
 
   // One barrier per k-tile: after a wave's own loads of tile kt have landed

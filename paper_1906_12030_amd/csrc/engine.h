@@ -13,10 +13,10 @@ namespace mera {
 // Arithmetic of one contraction.
 //   F64: double operands, FP64 MFMA (v_mfma_f64_16x16x4f64).
 //   F32: float operands, FP32 MFMA (v_mfma_f32_16x16x4f32).
-//   B3 : operands and FP32 intermediates stored as split words (bf16 hi of
-//        the FP32 value in the upper half, bf16 lo of the remainder in the lower
-//        half; see pack_split in tc_common.h), three BF16 MFMA products
-//        (hi*hi + hi*lo + lo*hi) accumulated in FP32.
+//   B3 : operands and FP32 intermediates stored as split tensors (bf16 hi of
+//        the FP32 value and bf16 lo of the remainder, the halves of 8
+//        consecutive elements grouped; see split_hi in tc_common.h), three BF16
+//        MFMA products (hi*hi + hi*lo + lo*hi) accumulated in FP32.
 enum class Arith : int { F64 = 0, F32 = 1, B3 = 2 };
 
 // Sizes of the index labels used by contraction specs (one char per label).
@@ -33,9 +33,9 @@ struct LabelDims {
 // C[lc] = alpha * sum_{shared labels} A[la] * B[lb] + beta * C[lc].
 // Each operand is dense row-major in the order of its label string.  Labels
 // shared by A and B and absent from C are summed; labels of C come from exactly
-// one of A and B.  A and B hold double for F64, float for F32 and split words
-// for B3; C holds double when c_f64 and otherwise float (F32) or split words
-// (B3).  K must be at least 1.  Returns hipSuccess or the launch
+// one of A and B.  A and B hold double for F64, float for F32 and split
+// tensors for B3 (32-byte aligned); C holds double when c_f64 and otherwise
+// float (F32) or a split tensor (B3).  K must be at least 1.  Returns hipSuccess or the launch
 // error.  `flops` (nullable) is increased by 2*M*N*K.  `scratch` (device,
 // nullable) of scratch_elems doubles lets the engine split long k ranges over
 // several workgroups (partial sums reduced in a fixed order) when the output
@@ -65,9 +65,10 @@ hipError_t run_mfma_peak(int kind, float* out, int blocks, int iters, hipStream_
 double mfma_peak_flops_per_wave_iter(int kind);
 
 // ---- auxiliary kernels (aux.hip) ----
-// y[i] = (float) x[i]; with split, y holds split words (hi|lo bf16) of (float) x[i]
+// y[i] = (float) x[i]; with split, y is the split tensor of (float) x (see
+// split_hi in tc_common.h; 32 * ceil(n / 8) bytes)
 hipError_t launch_to_f32(const double* x, float* y, int64_t n, bool split, hipStream_t s);
-// y = split words of the d^6 density x[i j k I J K], stored as y[j k J K i I]
+// y = split tensor of the d^6 density x[i j k I J K], stored as y[j k J K i I]
 hipError_t launch_rho_to_split_perm(const double* x, float* y, int32_t d, hipStream_t s);
 // y[i] = a * x[i]
 hipError_t launch_scale(const double* x, double* y, double a, int64_t n, hipStream_t s);

@@ -86,8 +86,10 @@ struct Ctx {
   std::vector<std::string>* plans = nullptr;  // dry mode: kernel choice of every contraction
 
   size_t elem() const { return ar == Arith::F64 ? 8 : 4; }
-  // reserve `count` elements of `bytes_per` bytes, 256-byte aligned
+  // reserve `count` elements of `bytes_per` bytes, 256-byte aligned (split
+  // tensors, the 4-byte elements of the split-bf16 path, in whole 8-element groups)
   void* take(size_t count, size_t bytes_per) {
+    if (ar == Arith::B3 && bytes_per == 4) count = (count + 7) & ~size_t(7);
     off = (off + 255) & ~size_t(255);
     void* p = dry ? nullptr : base + off;
     off += count * bytes_per;
@@ -146,7 +148,7 @@ int64_t ipow(int64_t b, int e) {
   return r;
 }
 
-// Layer tensors in the working type (converted copies for F32; split words for B3).
+// Layer tensors in the working type (converted copies for F32; split tensors for B3).
 struct LayerT {
   const void* u;
   const void* w;
@@ -347,13 +349,31 @@ int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_
   return 0;
 }
 
+// Rows of the sliced leg per slice must be a multiple of this: a slice of the
+// split-bf16 pieces N and M1 (din^3 * dout elements per row) has to start on a
+// whole 8-element group of the split tensor.
+int64_t slice_row_multiple(Arith ar, int64_t din, int64_t dout) {
+  if (ar != Arith::B3) return 1;
+  const int64_t e = din * din * din * dout;
+  return e % 8 == 0 ? 1 : e % 4 == 0 ? 2 : e % 2 == 0 ? 4 : 8;
+}
+
+// Slice count with the fewest slices allowed by slice_row_multiple (din
+// unsliced rows when even that is not possible).
+int max_slices(Arith ar, int64_t din, int64_t dout) {
+  const int64_t r = slice_row_multiple(ar, din, dout);
+  return r >= din ? 1 : (int)((din + r - 1) / r);
+}
+
 // Smallest slice count whose workspace fits ws_bytes for a body taking the
-// slice count (1 = unsliced); 0 if even one slice per leg value does not fit.
+// slice count (1 = unsliced); 0 if even the most slices allowed do not fit.
 template <typename Body>
-int choose_slices(const Ctx& proto, int64_t din, size_t ws_bytes, Body&& body) {
+int choose_slices(const Ctx& proto, int64_t din, int64_t dout, size_t ws_bytes, Body&& body) {
+  const int64_t rmul = slice_row_multiple(proto.ar, din, dout);
   for (int s = 1; s <= din; ++s) {
     const int64_t R = (din + s - 1) / s;
     if (s > 1 && (din + R - 1) / R != s) continue;  // same extent as a smaller count
+    if (s > 1 && R % rmul != 0) continue;            // slices must start on whole groups
     Ctx dry = proto;
     dry.dry = true;
     dry.off = 0;
@@ -864,7 +884,7 @@ int mera_descend(const mera_layer* layer, const double* rho_in_d, double* rho_ou
   }
   Ctx cx;
   cx.ar = arith_of(precision);
-  const int S = choose_slices(cx, layer->din, ws_bytes, [&](Ctx& c, int s) {
+  const int S = choose_slices(cx, layer->din, layer->dout, ws_bytes, [&](Ctx& c, int s) {
     run_descend(c, layer, rho_in_d, rho_out_d, placement, s);
   });
   if (S == 0) {
@@ -887,7 +907,7 @@ int mera_descend_noalloc(const mera_layer* layer, const double* rho_in_d, double
   }
   Ctx cx;
   cx.ar = arith_of(precision);
-  const int S = choose_slices(cx, layer->din, kNoAllocScratchBytes, [&](Ctx& c, int s) {
+  const int S = choose_slices(cx, layer->din, layer->dout, kNoAllocScratchBytes, [&](Ctx& c, int s) {
     run_descend(c, layer, rho_in_d, rho_out_d, placement, s);
   });
   if (S == 0) {
@@ -1130,7 +1150,7 @@ int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, dou
       status = MERA_ENOTCONV;
     }
   };
-  S = choose_slices(cx, d, ws_bytes, [&](Ctx& c, int s) {
+  S = choose_slices(cx, d, d, ws_bytes, [&](Ctx& c, int s) {
     S = s;
     body(c);
   });
@@ -1263,7 +1283,7 @@ size_t mera_workspace_bytes_min(int op, int32_t din, int32_t dout, int precision
   cx.ar = arith_of(precision);
   cx.dry = true;
   if (op == MERA_OP_DESCEND) {
-    run_descend(cx, &L, dummy, out, placement, din);
+    run_descend(cx, &L, dummy, out, placement, max_slices(cx.ar, din, dout));
     return cx.off;
   }
   const int64_t n = (int64_t)din * din * din;
@@ -1273,12 +1293,14 @@ size_t mera_workspace_bytes_min(int op, int32_t din, int32_t dout, int precision
   cx.take_d(4);
   const size_t mark = cx.off;
   cx.ar = Arith::F64;
-  run_descend(cx, &L, dummy, out, MERA_AVG, din);
+  // the FP64 and reduced-precision descends of the fixed point share one slice count
+  const int S = max_slices(arith_of(precision), din, din);
+  run_descend(cx, &L, dummy, out, MERA_AVG, S);
   const size_t hi = cx.off;
   if (refine) {
     cx.off = mark;
     cx.ar = arith_of(precision);
-    run_descend(cx, &L, dummy, out, MERA_AVG, din);
+    run_descend(cx, &L, dummy, out, MERA_AVG, S);
   }
   return std::max(hi, cx.off);
 }

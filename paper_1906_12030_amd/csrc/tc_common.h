@@ -32,7 +32,7 @@ struct TcArgs {
   int32_t tiles_m, tiles_n, per_xcd, group_m;
   int32_t splits, kchunk;  // k range of split s: [s*kchunk, min(K, (s+1)*kchunk))
   int32_t cvec;            // 64-wide output column spans are contiguous (vector stores)
-  int32_t csplit;          // FP32 C is stored as split words (see pack_split)
+  int32_t csplit;          // FP32 C is a split tensor (see split_hi)
   // Large-tile kernel only: 0 = C's innermost leg is an n leg (stores along
   // n); 1 = it is the innermost m leg, with unit stride, a multiple of 4 long
   // and every other C stride a multiple of 4 (four consecutive rows form one
@@ -40,17 +40,40 @@ struct TcArgs {
   int32_t cm;
 };
 
-// Split word: a 4-byte element holding x as two bf16 halves, hi = bf16_rne(x)
-// in bits 31..16 and lo = bf16_rne(x - hi) in bits 15..0.  The split-bf16
-// kernel reads its operands in this form, so the split of each value is done
-// once by the kernel that produces it instead of once per tile load.
-__device__ __forceinline__ uint32_t pack_split(float x) {
-  const __bf16 hi = (__bf16)x;
-  const __bf16 lo = (__bf16)(x - (float)hi);
-  return ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16) | __builtin_bit_cast(uint16_t, lo);
+// Split tensors.  The split-bf16 path keeps every FP32 value x as two bf16
+// numbers, hi = bf16_rne(x) and lo = bf16_rne(x - hi), in 4 bytes per element,
+// grouped by 8 consecutive elements: the 32-byte group i / 8 holds the hi halves
+// of its 8 elements (bytes 0..15, element i % 8 at halfword i % 8), then their lo
+// halves (bytes 16..31).  A 16-byte read of either half of a group is one bf16x8
+// MFMA operand, so the split of each value is done once, by the kernel that
+// produces the tensor, and the loaders need no regrouping.  A split tensor of n
+// elements occupies 32 * ceil(n / 8) bytes and starts 32-byte aligned.
+__device__ __forceinline__ int64_t split_hi(int64_t i) { return ((i >> 3) << 4) | (i & 7); }
+__device__ __forceinline__ uint16_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// element i of the split tensor at base: store x / load hi + lo
+__device__ __forceinline__ void split_store(void* base, int64_t i, float x) {
+  uint16_t* b = static_cast<uint16_t*>(base) + split_hi(i);
+  const uint16_t h = bf16_bits(x);
+  b[0] = h;
+  b[8] = bf16_bits(x - bf16_value(h));
 }
-__device__ __forceinline__ float unpack_split(uint32_t w) {
-  return __uint_as_float(w & 0xffff0000u) + __uint_as_float(w << 16);
+__device__ __forceinline__ float split_load(const void* base, int64_t i) {
+  const uint16_t* b = static_cast<const uint16_t*>(base) + split_hi(i);
+  return bf16_value(b[0]) + bf16_value(b[8]);
+}
+// elements i .. i + 3 (i a multiple of 4, so they share a group): two 8-byte stores
+__device__ __forceinline__ void split_store4(void* base, int64_t i, const float (&x)[4]) {
+  typedef uint16_t h4_t __attribute__((ext_vector_type(4)));
+  h4_t h, l;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    h[e] = bf16_bits(x[e]);
+    l[e] = bf16_bits(x[e] - bf16_value(h[e]));
+  }
+  uint16_t* b = static_cast<uint16_t*>(base) + split_hi(i);
+  *reinterpret_cast<h4_t*>(b) = h;
+  *reinterpret_cast<h4_t*>(b + 8) = l;
 }
 
 // Offset of linear group index idx in operand x (Second = false) or y.
@@ -288,21 +311,50 @@ __device__ __forceinline__ void stage_c_offsets(const TcArgs& p, uint32_t m0, ui
   }
 }
 
-// Element of C as a number / a number as C's element (split words when
-// p.csplit; the bits travel in a float).
+// Element `off` of C as a number, and y stored there (a split tensor when
+// p.csplit).
 template <typename TC>
-__device__ __forceinline__ double load_c(const TcArgs& p, const TC* src) {
+__device__ __forceinline__ double load_c(const TcArgs& p, const TC* C, int64_t off) {
   if constexpr (sizeof(TC) == 4) {
-    if (p.csplit) return (double)unpack_split(__float_as_uint(*src));
+    if (p.csplit) return (double)split_load(C, off);
   }
-  return (double)*src;
+  return (double)C[off];
 }
 template <typename TC>
-__device__ __forceinline__ TC store_c(const TcArgs& p, double y) {
+__device__ __forceinline__ void store_c(const TcArgs& p, TC* C, int64_t off, double y) {
   if constexpr (sizeof(TC) == 4) {
-    if (p.csplit) return __uint_as_float(pack_split((float)y));
+    if (p.csplit) {
+      split_store(C, off, (float)y);
+      return;
+    }
   }
-  return (TC)y;
+  C[off] = (TC)y;
+}
+// Four consecutive elements off .. off + 3 of C (off a multiple of 4, 16-byte
+// aligned): y = alpha * x + beta * C, one vector store (two for double C, two
+// 8-byte stores for a split C).
+template <typename TC, typename X>
+__device__ __forceinline__ void store_c4(const TcArgs& p, TC* C, int64_t off, const X& x, double alpha,
+                                         double beta) {
+  double y[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    y[e] = alpha * (double)x[e];
+    if (beta != 0.0) y[e] += beta * load_c(p, C, off + e);
+  }
+  if constexpr (sizeof(TC) == 4) {
+    if (p.csplit) {
+      const float f[4] = {(float)y[0], (float)y[1], (float)y[2], (float)y[3]};
+      split_store4(C, off, f);
+      return;
+    }
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    *reinterpret_cast<f4v*>(C + off) = f4v{(float)y[0], (float)y[1], (float)y[2], (float)y[3]};
+  } else {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    *reinterpret_cast<d2v*>(C + off) = d2v{y[0], y[1]};
+    *reinterpret_cast<d2v*>(C + off + 2) = d2v{y[2], y[3]};
+  }
 }
 
 // Epilogue shared by the MFMA kernels.  Each wave owns a 64x64 block of the
@@ -356,39 +408,29 @@ __device__ __forceinline__ void write_tile(const TcArgs& p, ACC (&acc)[4][4], ui
       for (int e = 0; e < VA; ++e) v[e] = x[e];
       const int64_t co = cols[wn + col];
       if (vec && co >= 0) {
-        TC* dst = C + ro + co;
-        TC out[VA];
+        if constexpr (VA == 4) {
+          store_c4(p, C, ro + co, v, alpha, beta);
+        } else {  // two doubles from double accumulators: one 16-byte store
+          double y[VA];
 #pragma unroll
-        for (int e = 0; e < VA; ++e) {
-          double y = alpha * (double)v[e];
-          if (beta != 0.0) y += beta * load_c(p, dst + e);
-          out[e] = store_c<TC>(p, y);
-        }
-        if constexpr (sizeof(TC) * VA == 16) {
+          for (int e = 0; e < VA; ++e) {
+            y[e] = alpha * (double)v[e];
+            if (beta != 0.0) y[e] += beta * load_c(p, C, ro + co + e);
+          }
           typedef TC ot __attribute__((ext_vector_type(VA)));
           ot o;
 #pragma unroll
-          for (int e = 0; e < VA; ++e) o[e] = out[e];
-          *reinterpret_cast<ot*>(dst) = o;
-        } else {  // 4 doubles from float accumulators: two 16-byte stores
-          typedef TC ot __attribute__((ext_vector_type(2)));
-#pragma unroll
-          for (int h = 0; h < VA / 2; ++h) {
-            ot o;
-            o[0] = out[2 * h];
-            o[1] = out[2 * h + 1];
-            *reinterpret_cast<ot*>(dst + 2 * h) = o;
-          }
+          for (int e = 0; e < VA; ++e) o[e] = (TC)y[e];
+          *reinterpret_cast<ot*>(C + ro + co) = o;
         }
       } else {
 #pragma unroll
         for (int e = 0; e < VA; ++e) {
           const int64_t ce = cols[wn + col + e];
           if (ce < 0) continue;
-          TC* dst = C + ro + ce;
           double y = alpha * (double)v[e];
-          if (beta != 0.0) y += beta * load_c(p, dst);
-          *dst = store_c<TC>(p, y);
+          if (beta != 0.0) y += beta * load_c(p, C, ro + ce);
+          store_c(p, C, ro + ce, y);
         }
       }
     }

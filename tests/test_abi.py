@@ -69,7 +69,7 @@ def test_invalid_arguments_rejected_before_device(lib):
 
 def test_noalloc_descend_rejects_what_the_static_scratch_cannot_hold(lib):
     fake = 4096  # never dereferenced: the size check fails before any HIP call
-    for d, prec in ((14, 0), (15, 1), (15, 2), (24, 2)):
+    for d, prec in ((14, 0), (15, 1), (13, 2), (15, 2), (24, 2)):
         assert _lib.mera_descend_noalloc(_layer(d, d), fake, fake, 2, prec, None) == _lib.MERA_EWORKSPACE
         assert b"static scratch" in lib.mera_last_error()
     assert _lib.mera_descend_noalloc(_layer(4, 17), fake, fake, 2, 0, None) == _lib.MERA_ESHAPE
@@ -78,10 +78,16 @@ def test_noalloc_descend_rejects_what_the_static_scratch_cannot_hold(lib):
     # the limit in the header is the one the library applies
     mib = int(re.search(r"#define MERA_NOALLOC_SCRATCH_MIB (\d+)",
                         open(os.path.join(ROOT, "include", "mera.h")).read()).group(1))
-    for d in (13, 14):
-        for prec in (0, 1, 2):
-            fits = _lib.mera_workspace_bytes_min(_lib.MERA_OP_DESCEND, d, d, prec, 2) <= mib << 20
-            assert fits == (d == 13 or prec != 0), (d, prec)
+    fits = {(d, prec): _lib.mera_workspace_bytes_min(_lib.MERA_OP_DESCEND, d, d, prec, 2) <= mib << 20
+            for d in range(2, 25) for prec in (0, 1, 2)}
+    # FP64 up to chi = 13, FP32 up to 14; split bf16 up to 12 and at 14 (at odd chi
+    # the slices of its split tensors must start on whole 8-element groups)
+    assert [d for d in range(2, 25) if fits[(d, 0)]] == list(range(2, 14))
+    assert [d for d in range(2, 25) if fits[(d, 1)]] == list(range(2, 15))
+    assert [d for d in range(2, 25) if fits[(d, 2)]] == list(range(2, 13)) + [14]
+    for (d, prec), ok in fits.items():
+        if not ok:
+            assert _lib.mera_descend_noalloc(_layer(d, d), fake, fake, 2, prec, None) == _lib.MERA_EWORKSPACE
 
 
 def test_workspace_too_small_and_misaligned(lib):
