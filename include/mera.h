@@ -75,7 +75,10 @@ typedef enum {
   MERA_OP_ENV_W = 3,
   MERA_OP_POLAR = 4,        /* din = rows, dout = cols of the blocked environment */
   MERA_OP_FIXED_POINT = 5,  /* din = dout = d of the scale-invariant layer */
-  MERA_OP_ENERGY = 6
+  MERA_OP_ENERGY = 6,
+  MERA_OP_TREE_ASCEND = 7,   /* binary tree network calls (mera_tree_*) */
+  MERA_OP_TREE_DESCEND = 8,
+  MERA_OP_TREE_ENV_W = 9
 } mera_op;
 
 /* One MERA layer: disentangler u (din^4) and isometry w (din*din*dout), both
@@ -174,6 +177,31 @@ int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* o
  * Errors: MERA_EINVAL also for a negative or non-finite tol. */
 int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, double tol, int precision,
                          double* resid_d, void* ws_d, size_t ws_bytes, void* hip_stream);
+
+/* Binary tree network (Sec. I, Fig. 1a): a layer of isometries w only, the
+ * binary MERA with identity disentanglers (u[a,b,c,d] = delta_ac delta_bd).
+ * Same conventions as the MERA calls: w[a,b,c] (din*din*dout, lower legs
+ * first), three-site operators/densities [i1,i2,i3, j1,j2,j3], windows LEFT
+ * (the right child of the left isometry and both children of the centre one)
+ * and RIGHT (both children of the centre isometry and the left child of the
+ * right one) under the coarse window, AVG = (LEFT + RIGHT)/2.  Equal to
+ * mera_descend / mera_ascend / mera_env_w with u = identity (the isometry whose
+ * children are both traced enters through w^T w, also off the isometry
+ * manifold), at O(din^6 dout) work per call instead of O(din^6 dout^3).
+ * Workspace: mera_workspace_bytes(MERA_OP_TREE_*, din, dout, precision,
+ * placement).  Errors and asynchrony as for mera_descend. */
+int mera_tree_descend(int32_t din, int32_t dout, const double* w_d, const double* rho_in_d,
+                      double* rho_out_d, int placement, int precision, void* ws_d, size_t ws_bytes,
+                      void* hip_stream);
+int mera_tree_ascend(int32_t din, int32_t dout, const double* w_d, const double* h_in_d,
+                     double* h_out_d, int placement, int precision, void* ws_d, size_t ws_bytes,
+                     void* hip_stream);
+/* env_w_d (din*din*dout) = d tr(h D_P(rho)) / d(ket copies of w): three
+ * contributions per window (left, centre and right isometry), halved and summed
+ * for AVG.  Euler: <env_w, w> = 3 e. */
+int mera_tree_env_w(int32_t din, int32_t dout, const double* w_d, const double* h_d,
+                    const double* rho_d, double* env_w_d, int placement, int precision, void* ws_d,
+                    size_t ws_bytes, void* hip_stream);
 
 /* Energy (Sec. II.B): e = tr(h rho) = sum_ij h_ij rho_ji for n x n matrices
  * (n = d^3), FP64 with a fixed reduction order (bitwise reproducible).

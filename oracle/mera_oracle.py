@@ -732,6 +732,63 @@ def descend_dense(u, w, rho):
 
 
 # ---------------------------------------------------------------------------
+# Binary tree network (Fig. 1a): the cone without disentanglers
+# ---------------------------------------------------------------------------
+# In a layer of the tree, coarse site k owns an isometry w[a, b, c] whose lower
+# legs are fine sites (2k, 2k+1).  Under the coarse window (k-1, k, k+1) the
+# three-site fine window L = (2k-1, 2k, 2k+1) is the right child of the left
+# isometry and both children of the centre one; R = (2k, 2k+1, 2k+2) is both
+# children of the centre and the left child of the right isometry.  Every
+# other lower leg of the three isometries is traced between ket and bra, so
+# the third isometry enters only through w^T w on its coarse leg.  With
+# identity disentanglers the binary MERA cone is this network.
+_TREE_KET = {"wL": "xai", "wC": "bcj", "wR": "dyk"}
+
+
+def _tree_cone(placement):
+    """(bra labels, fine labels) of the tree cone; ket labels in _TREE_KET, the
+    coarse density's labels are 'ijkIJK'."""
+    if placement == "L":
+        bra = {"wL": "xAI", "wC": "BCJ", "wR": "dyK"}
+        fine = "abcABC"
+    elif placement == "R":
+        bra = {"wL": "xaI", "wC": "BCJ", "wR": "DyK"}
+        fine = "bcdBCD"
+    else:
+        raise ValueError(placement)
+    return bra, fine
+
+
+def tree_descend(w, rho, placement):
+    """Three-site density of window P from the coarse density rho (tree network)."""
+    bra, fine = _tree_cone(placement)
+    subs = list(_TREE_KET.values()) + list(bra.values()) + ["ijkIJK"]
+    return _einsum(subs, [w] * 6 + [rho], fine)
+
+
+def tree_ascend(w, op, placement):
+    """Coarse three-site operator from op on window P: the adjoint of tree_descend."""
+    bra, fine = _tree_cone(placement)
+    subs = list(_TREE_KET.values()) + list(bra.values()) + [fine]
+    return _einsum(subs, [w] * 6 + [op], "ijkIJK")
+
+
+def tree_env_w(w, h, rho, placement="AVG"):
+    """d tr(h D_P(rho)) / d(ket copies of w) for the tree: three contributions per
+    window (left, centre and right isometry), halved and summed for AVG."""
+    places = ("L", "R") if placement == "AVG" else (placement,)
+    scale = 0.5 if placement == "AVG" else 1.0
+    env = np.zeros_like(w)
+    for p in places:
+        bra, fine = _tree_cone(p)
+        for copy, lbl in _TREE_KET.items():
+            subs = [l for c, l in _TREE_KET.items() if c != copy] + list(bra.values())
+            subs += ["ijkIJK", _transpose_label(fine)]
+            env += _einsum(subs, [w] * 5 + [rho, h], lbl)
+    return scale * env
+
+
+# ---------------------------------------------------------------------------
 # Binary tree (u = identity) descending superoperator, written independently
 # ---------------------------------------------------------------------------
 def descend_tree(w, rho):

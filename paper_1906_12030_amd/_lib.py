@@ -16,14 +16,15 @@ MERA_OK, MERA_EINVAL, MERA_ESHAPE, MERA_EWORKSPACE, MERA_EDEVICE, MERA_ENUMERIC,
 MERA_LEFT, MERA_RIGHT, MERA_AVG = 0, 1, 2
 MERA_FP64, MERA_FP32, MERA_BF16X3 = 0, 1, 2
 (MERA_OP_ASCEND, MERA_OP_DESCEND, MERA_OP_ENV_U, MERA_OP_ENV_W, MERA_OP_POLAR,
- MERA_OP_FIXED_POINT, MERA_OP_ENERGY) = range(7)
+ MERA_OP_FIXED_POINT, MERA_OP_ENERGY, MERA_OP_TREE_ASCEND, MERA_OP_TREE_DESCEND,
+ MERA_OP_TREE_ENV_W) = range(10)
 
 EXPORTED = (
     "mera_ascend", "mera_descend", "mera_env_u", "mera_env_w", "mera_polar_update",
     "mera_fixed_point_rho", "mera_energy", "mera_tfim_hamiltonian", "mera_workspace_bytes",
     "mera_strerror", "mera_last_error", "mera_flops", "mera_profile_begin", "mera_profile_end",
     "mera_workspace_bytes_min", "mera_mfma_peak", "mera_contract", "mera_schedule_plan",
-    "mera_descend_noalloc",
+    "mera_descend_noalloc", "mera_tree_descend", "mera_tree_ascend", "mera_tree_env_w",
 )
 
 
@@ -59,6 +60,11 @@ def load() -> ctypes.CDLL:
     lib.mera_ascend.argtypes = [lp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
     lib.mera_descend.argtypes = [lp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
     lib.mera_descend_noalloc.argtypes = [lp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    for name in ("mera_tree_descend", "mera_tree_ascend"):
+        getattr(lib, name).argtypes = [i32, i32, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
+        getattr(lib, name).restype = ctypes.c_int
+    lib.mera_tree_env_w.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
+    lib.mera_tree_env_w.restype = ctypes.c_int
     lib.mera_descend_noalloc.restype = ctypes.c_int
     lib.mera_env_u.argtypes = [lp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
     lib.mera_env_w.argtypes = [lp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
@@ -105,6 +111,20 @@ def check(status: int, where: str) -> None:
 
 def mera_descend_noalloc(layer, rho_in_d, rho_out_d, placement, precision, stream):
     return load().mera_descend_noalloc(ctypes.byref(layer), rho_in_d, rho_out_d, placement, precision, stream)
+
+
+def mera_tree_descend(din, dout, w_d, rho_in_d, rho_out_d, placement, precision, ws_d, ws_bytes, stream):
+    return load().mera_tree_descend(din, dout, w_d, rho_in_d, rho_out_d, placement, precision, ws_d, ws_bytes,
+                                    stream)
+
+
+def mera_tree_ascend(din, dout, w_d, h_in_d, h_out_d, placement, precision, ws_d, ws_bytes, stream):
+    return load().mera_tree_ascend(din, dout, w_d, h_in_d, h_out_d, placement, precision, ws_d, ws_bytes, stream)
+
+
+def mera_tree_env_w(din, dout, w_d, h_d, rho_d, env_d, placement, precision, ws_d, ws_bytes, stream):
+    return load().mera_tree_env_w(din, dout, w_d, h_d, rho_d, env_d, placement, precision, ws_d, ws_bytes,
+                                  stream)
 
 
 def mera_ascend(layer, h_in_d, h_out_d, placement, precision, ws_d, ws_bytes, stream):

@@ -499,6 +499,172 @@ int run_env(Ctx& cx, const mera_layer* L, const double* h_in, const double* rho_
 // ---------------------------------------------------------------------------
 // checks
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Binary tree network (Fig. 1a): the layer without disentanglers.  Labels:
+// fine ket a b c d, bra A B C D (din); coarse ket i j k, bra I J K (dout);
+// outer legs x, y (din) traced between ket and bra; z a leg of extent 1 (outer
+// products).  Left isometry w[x a i] (fine site a = its right child), centre
+// w[b c j], right w[d y k] (fine site d = its left child).  The isometry whose
+// lower legs are both outside the window enters through P = w^T w on its
+// coarse leg, the side isometry through E[a A i I] = sum_x w[x a i] w[x A I]
+// (left) or E[d D k K] = sum_y w[d y k] w[D y K] (right):
+//   D_L(rho)[a b c A B C] = sum rho[i j k I J K] P[k K] E[a A i I] w[b c j] w[B C J]
+//   D_R(rho)[b c d B C D] = sum rho[i j k I J K] P[i I] w[b c j] w[B C J] E[d D k K]
+// Every step is at most din^6 dout multiply-adds (against din^6 dout^3 for
+// the MERA cone).
+// ---------------------------------------------------------------------------
+struct TreeParts {
+  const void* w;
+  void *pr, *el, *pl, *er;  // P[k K] of the right isometry, E_L[a A i I], P[i I], E_R[d D k K]
+};
+
+TreeParts tree_parts(Ctx& cx, const double* w_d, int64_t din, int64_t dout, int placement) {
+  cx.dims.set("z", 1);
+  TreeParts t{};
+  if (cx.ar == Arith::F64) {
+    t.w = w_d;
+  } else {
+    void* wt = cx.take_t(din * din * dout);
+    if (!cx.dry) cx.check(mera::launch_to_f32(w_d, static_cast<float*>(wt), din * din * dout,
+                                              cx.ar == Arith::B3, cx.s), "to_f32(w)");
+    t.w = wt;
+  }
+  if (placement != MERA_RIGHT) {
+    t.pr = cx.take_t(dout * dout);
+    t.el = cx.take_t(din * din * dout * dout);
+    cx.c(t.w, "dyk", t.w, "dyK", t.pr, "kK", false, 1.0, 0.0);
+    cx.c(t.w, "xai", t.w, "xAI", t.el, "aAiI", false, 1.0, 0.0);
+  }
+  if (placement != MERA_LEFT) {
+    t.pl = cx.take_t(dout * dout);
+    t.er = cx.take_t(din * din * dout * dout);
+    cx.c(t.w, "xai", t.w, "xaI", t.pl, "iI", false, 1.0, 0.0);
+    cx.c(t.w, "dyk", t.w, "DyK", t.er, "dDkK", false, 1.0, 0.0);
+  }
+  return t;
+}
+
+int run_tree_descend(Ctx& cx, int64_t din, int64_t dout, const double* w_d, const double* rho_in,
+                     double* rho_out, int placement) {
+  set_dims(cx, (int)din, (int)dout);
+  const TreeParts t = tree_parts(cx, w_d, din, dout, placement);
+  const void* rho = working_op(cx, rho_in, ipow(dout, 6));
+  void* r2 = cx.take_t(ipow(dout, 4));
+  void* y1 = cx.take_t(din * din * dout * dout);
+  void* y2 = cx.take_t(ipow(din, 4) * dout);
+  const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
+  bool first = true;
+  if (placement != MERA_RIGHT) {
+    cx.c(rho, "ijkIJK", t.pr, "kK", r2, "ijIJ", false, 1.0, 0.0);
+    cx.c(r2, "ijIJ", t.el, "aAiI", y1, "aAjJ", false, 1.0, 0.0);
+    cx.c(y1, "aAjJ", t.w, "bcj", y2, "aAJbc", false, 1.0, 0.0);
+    cx.c(y2, "aAJbc", t.w, "BCJ", rho_out, "abcABC", true, wgt, 0.0);
+    first = false;
+  }
+  if (placement != MERA_LEFT) {
+    cx.c(rho, "ijkIJK", t.pl, "iI", r2, "jkJK", false, 1.0, 0.0);
+    cx.c(r2, "jkJK", t.er, "dDkK", y1, "dDjJ", false, 1.0, 0.0);
+    cx.c(y1, "dDjJ", t.w, "bcj", y2, "dDJbc", false, 1.0, 0.0);
+    cx.c(y2, "dDJbc", t.w, "BCJ", rho_out, "bcdBCD", true, wgt, first ? 0.0 : 1.0);
+  }
+  return 0;
+}
+
+int run_tree_ascend(Ctx& cx, int64_t din, int64_t dout, const double* w_d, const double* o_in,
+                    double* o_out, int placement) {
+  set_dims(cx, (int)din, (int)dout);
+  const TreeParts t = tree_parts(cx, w_d, din, dout, placement);
+  const void* o = working_op(cx, o_in, ipow(din, 6));
+  void* v1 = cx.take_t(ipow(din, 5) * dout);
+  void* v2 = cx.take_t(din * din * dout * dout);
+  void* v3 = cx.take_t(ipow(dout, 4));
+  const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
+  bool first = true;
+  if (placement != MERA_RIGHT) {  // adjoint of D_L: the traced site comes back as P
+    cx.c(o, "abcABC", t.w, "BCJ", v1, "abcAJ", false, 1.0, 0.0);
+    cx.c(v1, "abcAJ", t.w, "bcj", v2, "aAjJ", false, 1.0, 0.0);
+    cx.c(v2, "aAjJ", t.el, "aAiI", v3, "ijIJ", false, 1.0, 0.0);
+    cx.c(v3, "ijIJz", t.pr, "kKz", o_out, "ijkIJK", true, wgt, 0.0);
+    first = false;
+  }
+  if (placement != MERA_LEFT) {
+    cx.c(o, "bcdBCD", t.w, "BCJ", v1, "bcdDJ", false, 1.0, 0.0);
+    cx.c(v1, "bcdDJ", t.w, "bcj", v2, "dDjJ", false, 1.0, 0.0);
+    cx.c(v2, "dDjJ", t.er, "dDkK", v3, "jkJK", false, 1.0, 0.0);
+    cx.c(t.pl, "iIz", v3, "jkJKz", o_out, "ijkIJK", true, wgt, first ? 0.0 : 1.0);
+  }
+  return 0;
+}
+
+// Environment of w in the tree: the derivative of e = tr(h D_P(rho)) with
+// respect to the ket copies of the left, centre and right isometries (three
+// contributions per window; the isometry outside the window through P).
+int run_tree_env_w(Ctx& cx, int64_t din, int64_t dout, const double* w_d, const double* h_in,
+                   const double* rho_in, double* env, int placement) {
+  set_dims(cx, (int)din, (int)dout);
+  const TreeParts t = tree_parts(cx, w_d, din, dout, placement);
+  const void* h = working_op(cx, h_in, ipow(din, 6));
+  const void* rho = working_op(cx, rho_in, ipow(dout, 6));
+  void* r2 = cx.take_t(ipow(dout, 4));                // R12 / R23
+  void* y1 = cx.take_t(din * din * dout * dout);      // forward: R . E
+  void* q1 = cx.take_t(ipow(din, 5) * dout);          // cotangent . bra centre isometry
+  void* q = cx.take_t(din * din * dout * dout);       // ... . ket centre isometry
+  void* ge = cx.take_t(din * din * dout * dout);      // d e / d E
+  void* hc = cx.take_t(ipow(dout, 4));                // d e / d R
+  void* gp = cx.take_t(dout * dout);                  // d e / d P
+  const double wgt = placement == MERA_AVG ? 0.5 : 1.0;
+  bool first = true;
+  auto acc = [&](const void* A, const char* la, const void* B, const char* lb, const char* lc) {
+    cx.c(A, la, B, lb, env, lc, true, wgt, first ? 0.0 : 1.0);
+    first = false;
+  };
+  if (placement != MERA_RIGHT) {
+    cx.c(rho, "ijkIJK", t.pr, "kK", r2, "ijIJ", false, 1.0, 0.0);
+    cx.c(r2, "ijIJ", t.el, "aAiI", y1, "aAjJ", false, 1.0, 0.0);
+    cx.c(h, "ABCabc", t.w, "BCJ", q1, "abcAJ", false, 1.0, 0.0);
+    cx.c(q1, "abcAJ", t.w, "bcj", q, "aAjJ", false, 1.0, 0.0);
+    acc(q1, "abcAJ", y1, "aAjJ", "bcj");                                   // centre
+    cx.c(q, "aAjJ", r2, "ijIJ", ge, "aAiI", false, 1.0, 0.0);
+    acc(ge, "aAiI", t.w, "xAI", "xai");                                    // left (in E_L)
+    cx.c(q, "aAjJ", t.el, "aAiI", hc, "ijIJ", false, 1.0, 0.0);
+    cx.c(rho, "ijkIJK", hc, "ijIJ", gp, "kK", false, 1.0, 0.0);
+    acc(gp, "kK", t.w, "dyK", "dyk");                                      // right (in P)
+  }
+  if (placement != MERA_LEFT) {
+    cx.c(rho, "ijkIJK", t.pl, "iI", r2, "jkJK", false, 1.0, 0.0);
+    cx.c(r2, "jkJK", t.er, "dDkK", y1, "dDjJ", false, 1.0, 0.0);
+    cx.c(h, "BCDbcd", t.w, "BCJ", q1, "bcdDJ", false, 1.0, 0.0);
+    cx.c(q1, "bcdDJ", t.w, "bcj", q, "dDjJ", false, 1.0, 0.0);
+    acc(q1, "bcdDJ", y1, "dDjJ", "bcj");                                   // centre
+    cx.c(q, "dDjJ", r2, "jkJK", ge, "dDkK", false, 1.0, 0.0);
+    acc(ge, "dDkK", t.w, "DyK", "dyk");                                    // right (in E_R)
+    cx.c(q, "dDjJ", t.er, "dDkK", hc, "jkJK", false, 1.0, 0.0);
+    cx.c(rho, "ijkIJK", hc, "jkJK", gp, "iI", false, 1.0, 0.0);
+    acc(gp, "iI", t.w, "xaI", "xai");                                      // left (in P)
+  }
+  return 0;
+}
+
+int check_tree(int32_t din, int32_t dout, const double* w_d) {
+  if (!w_d) {
+    set_err("isometry pointer is null");
+    return MERA_EINVAL;
+  }
+  if (din < 1 || dout < 1) {
+    set_err("dimensions must be positive");
+    return MERA_ESHAPE;
+  }
+  if ((int64_t)dout > (int64_t)din * din) {
+    set_err("dout > din^2: no isometry exists");
+    return MERA_ESHAPE;
+  }
+  if (ipow(din, 6) * dout >= (int64_t(1) << 40) || ipow(dout, 6) >= (int64_t(1) << 40)) {
+    set_err("layer too large");
+    return MERA_ESHAPE;
+  }
+  return MERA_OK;
+}
+
 int check_layer(const mera_layer* L) {
   if (!L) {
     set_err("layer is null");
@@ -922,6 +1088,60 @@ int mera_descend_noalloc(const mera_layer* layer, const double* rho_in_d, double
                      [&](Ctx& c) { run_descend(c, layer, rho_in_d, rho_out_d, placement, S); });
 }
 
+int mera_tree_descend(int32_t din, int32_t dout, const double* w_d, const double* rho_in_d,
+                      double* rho_out_d, int placement, int precision, void* ws_d, size_t ws_bytes,
+                      void* hip_stream) {
+  OpTag tag(MERA_OP_TREE_DESCEND);
+  int st = check_tree(din, dout, w_d);
+  if (st) return st;
+  if ((st = check_enum(placement, precision))) return st;
+  if (!rho_in_d || !rho_out_d) {
+    set_err("null tensor pointer");
+    return MERA_EINVAL;
+  }
+  Ctx cx;
+  cx.ar = arith_of(precision);
+  return run_checked(cx, ws_d, ws_bytes, hip_stream, [&](Ctx& c) {
+    run_tree_descend(c, din, dout, w_d, rho_in_d, rho_out_d, placement);
+  });
+}
+
+int mera_tree_ascend(int32_t din, int32_t dout, const double* w_d, const double* h_in_d,
+                     double* h_out_d, int placement, int precision, void* ws_d, size_t ws_bytes,
+                     void* hip_stream) {
+  OpTag tag(MERA_OP_TREE_ASCEND);
+  int st = check_tree(din, dout, w_d);
+  if (st) return st;
+  if ((st = check_enum(placement, precision))) return st;
+  if (!h_in_d || !h_out_d) {
+    set_err("null tensor pointer");
+    return MERA_EINVAL;
+  }
+  Ctx cx;
+  cx.ar = arith_of(precision);
+  return run_checked(cx, ws_d, ws_bytes, hip_stream, [&](Ctx& c) {
+    run_tree_ascend(c, din, dout, w_d, h_in_d, h_out_d, placement);
+  });
+}
+
+int mera_tree_env_w(int32_t din, int32_t dout, const double* w_d, const double* h_d,
+                    const double* rho_d, double* env_w_d, int placement, int precision, void* ws_d,
+                    size_t ws_bytes, void* hip_stream) {
+  OpTag tag(MERA_OP_TREE_ENV_W);
+  int st = check_tree(din, dout, w_d);
+  if (st) return st;
+  if ((st = check_enum(placement, precision))) return st;
+  if (!h_d || !rho_d || !env_w_d) {
+    set_err("null tensor pointer");
+    return MERA_EINVAL;
+  }
+  Ctx cx;
+  cx.ar = arith_of(precision);
+  return run_checked(cx, ws_d, ws_bytes, hip_stream, [&](Ctx& c) {
+    run_tree_env_w(c, din, dout, w_d, h_d, rho_d, env_w_d, placement);
+  });
+}
+
 int mera_ascend(const mera_layer* layer, const double* h_in_d, double* h_out_d, int placement,
                 int precision, void* ws_d, size_t ws_bytes, void* hip_stream) {
   OpTag tag(MERA_OP_ASCEND);
@@ -1237,6 +1457,9 @@ size_t mera_workspace_bytes(int op, int32_t din, int32_t dout, int precision, in
   const double* dummy = reinterpret_cast<const double*>(256);
   double* out = reinterpret_cast<double*>(256);
   switch (op) {
+    case MERA_OP_TREE_ASCEND: run_tree_ascend(cx, din, dout, dummy, dummy, out, placement); break;
+    case MERA_OP_TREE_DESCEND: run_tree_descend(cx, din, dout, dummy, dummy, out, placement); break;
+    case MERA_OP_TREE_ENV_W: run_tree_env_w(cx, din, dout, dummy, dummy, dummy, out, placement); break;
     case MERA_OP_ASCEND: run_ascend(cx, &L, dummy, out, placement); break;
     case MERA_OP_DESCEND: run_descend(cx, &L, dummy, out, placement); break;
     case MERA_OP_ENV_U: run_env(cx, &L, dummy, dummy, out, placement, true); break;
@@ -1326,6 +1549,9 @@ int mera_schedule_plan(int op, int32_t din, int32_t dout, int precision, int pla
   cx.ar = arith_of(precision);
   cx.plans = &plans;
   switch (op) {
+    case MERA_OP_TREE_ASCEND: run_tree_ascend(cx, din, dout, dummy, dummy, o, placement); break;
+    case MERA_OP_TREE_DESCEND: run_tree_descend(cx, din, dout, dummy, dummy, o, placement); break;
+    case MERA_OP_TREE_ENV_W: run_tree_env_w(cx, din, dout, dummy, dummy, dummy, o, placement); break;
     case MERA_OP_ASCEND: run_ascend(cx, &L, dummy, o, placement); break;
     case MERA_OP_DESCEND: run_descend(cx, &L, dummy, o, placement); break;
     case MERA_OP_ENV_U: run_env(cx, &L, dummy, dummy, o, placement, true); break;
@@ -1355,6 +1581,9 @@ double mera_flops(int op, int32_t din, int32_t dout, int placement) {
   const double* dummy = reinterpret_cast<const double*>(256);
   double* out = reinterpret_cast<double*>(256);
   switch (op) {
+    case MERA_OP_TREE_ASCEND: run_tree_ascend(cx, din, dout, dummy, dummy, out, placement); break;
+    case MERA_OP_TREE_DESCEND: run_tree_descend(cx, din, dout, dummy, dummy, out, placement); break;
+    case MERA_OP_TREE_ENV_W: run_tree_env_w(cx, din, dout, dummy, dummy, dummy, out, placement); break;
     case MERA_OP_ASCEND: run_ascend(cx, &L, dummy, out, placement); break;
     case MERA_OP_DESCEND: run_descend(cx, &L, dummy, out, placement); break;
     case MERA_OP_ENV_U: run_env(cx, &L, dummy, dummy, out, placement, true); break;

@@ -11,8 +11,8 @@ the lowest eigenvector of its energy operator; then, top-down, update u and w
 of each layer from their environments and descend the density.
 
 The top state has d^4 amplitudes (d = the top bond dimension, 4 or 8): its
-energy operator (a d^4 x d^4 matrix) and its eigenvector are formed on the
-host in FP64; every contraction of the layers runs in the library.
+energy operator (a d^4 x d^4 matrix) and its lowest eigenvector are formed on
+the host in FP64 (numpy); every contraction of the layers runs in the library.
 """
 from __future__ import annotations
 
@@ -82,11 +82,16 @@ def energy(m: FiniteMera, h1: torch.Tensor, shift: float) -> float:
 
 
 def sweep(m: FiniteMera, h1: torch.Tensor, shift: float, precision="fp64", disentangle=True) -> float:
-    """One sweep; returns the energy per site after it.  disentangle=False keeps the
-    disentanglers fixed (identity disentanglers: the binary tree network of Fig. 1a)."""
+    """One sweep; returns the energy per site after it.  disentangle=False is the binary
+    tree network of Fig. 1a: the disentanglers are left out (the layers' u must be the
+    identity) and the layers run on the tree calls (mera_tree_*), which contract the
+    cone of isometries alone."""
     hs = [h1]
     for t in range(len(m.layers)):
-        hs.append(ops.ascend(m.layer(t), hs[-1], "avg", precision))
+        if disentangle:
+            hs.append(ops.ascend(m.layer(t), hs[-1], "avg", precision))
+        else:
+            hs.append(ops.tree_ascend(m.layers[t][1], hs[-1], "avg", precision))
     vals, vecs = np.linalg.eigh(top_operator(hs[-1].cpu().numpy()))
     d = hs[-1].shape[0]
     m.top = vecs[:, 0].reshape((d,) * 4)
@@ -94,8 +99,11 @@ def sweep(m: FiniteMera, h1: torch.Tensor, shift: float, precision="fp64", disen
     for t in reversed(range(len(m.layers))):
         if disentangle:
             m.layers[t][0] = ops.update_u(ops.env_u(m.layer(t), hs[t], rho, "avg", precision))
-        m.layers[t][1] = ops.update_w(ops.env_w(m.layer(t), hs[t], rho, "avg", precision))
-        rho = ops.descend(m.layer(t), rho, "avg", "fp64")
+            m.layers[t][1] = ops.update_w(ops.env_w(m.layer(t), hs[t], rho, "avg", precision))
+            rho = ops.descend(m.layer(t), rho, "avg", "fp64")
+        else:
+            m.layers[t][1] = ops.update_w(ops.tree_env_w(m.layers[t][1], hs[t], rho, "avg", precision))
+            rho = ops.tree_descend(m.layers[t][1], rho, "avg", "fp64")
     return float(ops.energy(h1, rho).item()) + shift
 
 

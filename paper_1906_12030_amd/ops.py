@@ -144,6 +144,54 @@ def env_w(layer: Layer, h: torch.Tensor, rho: torch.Tensor, placement="avg", pre
     return out
 
 
+def _tree_dims(w: torch.Tensor):
+    w = _dev(w)
+    din, din2, dout = (int(x) for x in w.shape)
+    if din2 != din:
+        raise ValueError("w must be din x din x dout")
+    return w, din, dout
+
+
+def tree_descend(w: torch.Tensor, rho: torch.Tensor, placement="avg", precision="fp64", out=None):
+    """Binary tree descend (Fig. 1a; the MERA with u = identity): dout^6 -> din^6."""
+    w, din, dout = _tree_dims(w)
+    rho = _dev(rho)
+    p, q = _place(placement), _prec(precision)
+    if out is None:
+        out = torch.empty((din,) * 6, dtype=torch.float64, device=rho.device)
+    ws, wsb = WORKSPACE.for_op(_lib.MERA_OP_TREE_DESCEND, din, dout, q, p, rho.device)
+    _lib.check(_lib.mera_tree_descend(din, dout, w.data_ptr(), rho.data_ptr(), out.data_ptr(), p, q, ws, wsb,
+                                      _stream(rho.device)), "mera_tree_descend")
+    return out
+
+
+def tree_ascend(w: torch.Tensor, h: torch.Tensor, placement="avg", precision="fp64", out=None):
+    """Binary tree ascend: din^6 -> dout^6."""
+    w, din, dout = _tree_dims(w)
+    h = _dev(h)
+    p, q = _place(placement), _prec(precision)
+    if out is None:
+        out = torch.empty((dout,) * 6, dtype=torch.float64, device=h.device)
+    ws, wsb = WORKSPACE.for_op(_lib.MERA_OP_TREE_ASCEND, din, dout, q, p, h.device)
+    _lib.check(_lib.mera_tree_ascend(din, dout, w.data_ptr(), h.data_ptr(), out.data_ptr(), p, q, ws, wsb,
+                                     _stream(h.device)), "mera_tree_ascend")
+    return out
+
+
+def tree_env_w(w: torch.Tensor, h: torch.Tensor, rho: torch.Tensor, placement="avg", precision="fp64",
+               out=None):
+    """Environment of w in the binary tree: din x din x dout."""
+    w, din, dout = _tree_dims(w)
+    h, rho = _dev(h), _dev(rho)
+    p, q = _place(placement), _prec(precision)
+    if out is None:
+        out = torch.empty((din, din, dout), dtype=torch.float64, device=h.device)
+    ws, wsb = WORKSPACE.for_op(_lib.MERA_OP_TREE_ENV_W, din, dout, q, p, h.device)
+    _lib.check(_lib.mera_tree_env_w(din, dout, w.data_ptr(), h.data_ptr(), rho.data_ptr(), out.data_ptr(), p, q,
+                                    ws, wsb, _stream(h.device)), "mera_tree_env_w")
+    return out
+
+
 def polar_update(env: torch.Tensor, rows: int, cols: int, out=None, check=True, want_sv=False):
     """-U V^T of env blocked as rows x cols (Sec. II.C, Fig. 5).
 
@@ -210,7 +258,9 @@ def tfim_hamiltonian(field: float = 1.0, device="cuda"):
 
 def flops(op: str, din: int, dout: int, placement="avg") -> float:
     ops = {"ascend": _lib.MERA_OP_ASCEND, "descend": _lib.MERA_OP_DESCEND, "env_u": _lib.MERA_OP_ENV_U,
-           "env_w": _lib.MERA_OP_ENV_W, "fixed_point_iter": _lib.MERA_OP_FIXED_POINT}
+           "env_w": _lib.MERA_OP_ENV_W, "fixed_point_iter": _lib.MERA_OP_FIXED_POINT,
+           "tree_ascend": _lib.MERA_OP_TREE_ASCEND, "tree_descend": _lib.MERA_OP_TREE_DESCEND,
+           "tree_env_w": _lib.MERA_OP_TREE_ENV_W}
     return _lib.mera_flops(ops[op], din, dout, _place(placement))
 
 

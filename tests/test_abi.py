@@ -243,3 +243,21 @@ def test_schedule_plan_argument_checks(lib):
     buf = ctypes.create_string_buffer(16)
     assert lib_.mera_schedule_plan(_lib.MERA_OP_ASCEND, 4, 4, 0, 2, buf, 16, ctypes.byref(need)) == 0
     assert len(buf.value) == 15 and need.value > 16
+
+
+def test_tree_calls_checks_and_cost(lib):
+    """Binary tree calls: host-side argument checks, and executed flops growing as din^6 dout
+    (against din^6 dout^3 for the MERA cone)."""
+    fake = 4096
+    assert _lib.mera_tree_descend(4, 17, fake, fake, fake, 2, 0, fake, 1 << 40, None) == _lib.MERA_ESHAPE
+    assert _lib.mera_tree_descend(4, 4, None, fake, fake, 2, 0, fake, 1 << 40, None) == _lib.MERA_EINVAL
+    assert _lib.mera_tree_ascend(4, 4, fake, fake, None, 2, 0, fake, 1 << 40, None) == _lib.MERA_EINVAL
+    assert _lib.mera_tree_env_w(4, 4, fake, fake, fake, fake, 3, 0, fake, 1 << 40, None) == _lib.MERA_EINVAL
+    need = _lib.mera_workspace_bytes(_lib.MERA_OP_TREE_ENV_W, 8, 8, 2, 2)
+    assert need > 0
+    assert _lib.mera_tree_env_w(8, 8, fake, fake, fake, fake, 2, 2, fake, need - 1, None) == _lib.MERA_EWORKSPACE
+    for op in (_lib.MERA_OP_TREE_ASCEND, _lib.MERA_OP_TREE_DESCEND, _lib.MERA_OP_TREE_ENV_W):
+        r = [_lib.mera_flops(op, d, d, 2) / d ** 7 for d in (16, 32, 64)]
+        assert all(3.5 < x < 8 for x in r), (op, r)
+        assert r[2] < r[1] < r[0]  # lower orders fade
+    assert _lib.mera_flops(_lib.MERA_OP_TREE_DESCEND, 24, 24, 2) < 1e-2 * _lib.mera_flops(_lib.MERA_OP_DESCEND, 24, 24, 2)

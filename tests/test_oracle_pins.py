@@ -364,3 +364,31 @@ def test_descend_slice_is_a_slice():
         full = O.descend_placement(u, w, rho, p)
         for k in range(3):
             assert np.abs(O.descend_placement_slice(u, w, rho, p, k) - full[k]).max() < 1e-14
+
+
+@pytest.mark.parametrize("din,dout", [(2, 4), (3, 3), (3, 2)])
+def test_tree_network_is_the_mera_with_identity_disentanglers(din, dout):
+    """The binary tree calls (Fig. 1a) equal the MERA network with u = identity, also for
+    tensors off the isometry manifold (the traced isometry enters through w^T w), and the
+    descent equals the separately written descend_tree."""
+    rng = np.random.default_rng(17 + din + dout)
+    _, w = I.random_layer(rng, din, dout)
+    one = np.eye(din * din).reshape((din,) * 4)
+    rho = I.random_density(rng, dout)
+    h = I.random_symmetric(rng, din)
+    for ww in (w, w + 0.3 * rng.standard_normal(w.shape)):
+        for p in ("L", "R"):
+            assert np.abs(O.tree_descend(ww, rho, p) - O.descend_placement(one, ww, rho, p)).max() < 1e-14
+            assert np.abs(O.tree_ascend(ww, h, p) - O.ascend_placement(one, ww, h, p)).max() < 1e-13
+        for p in ("L", "R", "AVG"):
+            assert np.abs(O.tree_env_w(ww, h, rho, p) - O.env_w(one, ww, h, rho, p)).max() < 1e-13
+    dl, dr = O.descend_tree(w, rho)
+    assert np.abs(dl - O.tree_descend(w, rho, "L")).max() < 1e-15
+    assert np.abs(dr - O.tree_descend(w, rho, "R")).max() < 1e-15
+    # adjointness and the Euler identity of the tree environment
+    o = rng.standard_normal((din,) * 6)
+    for p in ("L", "R"):
+        lhs = O.trace_product(O.tree_ascend(w, o, p), rho)
+        assert abs(lhs - O.trace_product(o, O.tree_descend(w, rho, p))) < 1e-12 * max(1.0, abs(lhs))
+    e = 0.5 * (O.trace_product(h, O.tree_descend(w, rho, "L")) + O.trace_product(h, O.tree_descend(w, rho, "R")))
+    assert abs(np.sum(O.tree_env_w(w, h, rho) * w) - 3 * e) < 1e-12
