@@ -97,6 +97,53 @@ def env_call_rates(m, h1, precision, ops, sweep, lib):
     return out
 
 
+def layer_update_times(m, h1, ops, sweep):
+    """One update of the scale-invariant layer at the current tensors, FP64, split into
+    contractions and polar (SVD) updates: the MERA (ascend, Env_u, Env_w, descend; polar of
+    u and of w) against the binary tree network (Fig. 1a: ascend, Env_w, descend of the tree
+    calls; polar of w).  Sec. III.B compares these shares (rho* about 40 times the u-SVD
+    for the MERA at chi = 16, about 3 for a tree)."""
+    import torch
+
+    h = sweep.ascend_chain(m, h1, "fp64")[-1]
+    si = m.si_layer()
+    u, w = m.si
+    din = int(w.shape[0])
+    torch.cuda.synchronize()
+
+    def timed(fn, reps=3):
+        best = None
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            out = fn()
+            b.record()
+            torch.cuda.synchronize()
+            t = a.elapsed_time(b) / 1e3
+            best = t if best is None else min(best, t)
+        return best, out
+
+    t_asc, _ = timed(lambda: ops.ascend(si, h, "avg", "fp64"))
+    t_eu, eu = timed(lambda: ops.env_u(si, h, m.rho_star, "avg", "fp64"))
+    t_ew, ew = timed(lambda: ops.env_w(si, h, m.rho_star, "avg", "fp64"))
+    t_d, _ = timed(lambda: ops.descend(si, m.rho_star, "avg", "fp64"))
+    t_pu, _ = timed(lambda: ops.update_u(eu))
+    t_pw, _ = timed(lambda: ops.update_w(ew))
+    tt_asc, _ = timed(lambda: ops.tree_ascend(w, h, "avg", "fp64"))
+    tt_ew, tew = timed(lambda: ops.tree_env_w(w, h, m.rho_star, "avg", "fp64"))
+    tt_d, _ = timed(lambda: ops.tree_descend(w, m.rho_star, "avg", "fp64"))
+    tt_pw, _ = timed(lambda: ops.update_w(tew))
+    mera_c = t_asc + t_eu + t_ew + t_d
+    tree_c = tt_asc + tt_ew + tt_d
+    return {"chi": din, "precision": "fp64",
+            "mera": {"contractions_s": round(mera_c, 5), "polar_s": round(t_pu + t_pw, 5),
+                     "polar_u_s": round(t_pu, 5), "contractions_over_polar": round(mera_c / (t_pu + t_pw), 2)},
+            "tree": {"contractions_s": round(tree_c, 5), "polar_s": round(tt_pw, 5),
+                     "contractions_over_polar": round(tree_c / tt_pw, 2)},
+            "mera_over_tree_contractions": round(mera_c / tree_c, 1)}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -430,6 +477,12 @@ def main():
 
     env_fp32 = env_call_rates(m, h1, "fp32", ops, sweep, _lib)
     print(f"# environment calls in fp32: {env_fp32}", file=sys.stderr, flush=True)
+    layer_times = layer_update_times(m, h1, ops, sweep)
+    fp_share = None
+    if phases.get("fixed_point"):
+        fp_share = round(phases["fixed_point"] / args.steps / layer_times["mera"]["polar_u_s"], 1)
+    print(f"# layer update MERA vs tree: {layer_times}; fixed point / u polar {fp_share}", file=sys.stderr,
+          flush=True)
 
     cpu = None
     scan = None
@@ -480,6 +533,8 @@ def main():
         "dE_one_sweep_fp32_environments_vs_fp64": abs(e_f32env - e_fp64) if (e_f32env is not None and e_fp64 is not None) else None,
         "env_contraction_fp32_in_sweep": env_f32_sweep,
         "evaluation_vs_oracle_chi24": oracle_eval,
+        "layer_update_mera_vs_tree": layer_times,
+        "fixed_point_over_u_polar": fp_share,
         "sweep_s_all_contractions_reduced": round(t_red, 4) if t_red else None,
         "speedup_all_reduced_vs_fp64": round(t_fp64 / t_red, 3) if (t_red and t_fp64) else None,
         "dE_one_sweep_all_reduced_vs_fp64": abs(e_red - e_fp64) if (e_red is not None and e_fp64 is not None) else None,

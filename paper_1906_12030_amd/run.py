@@ -99,7 +99,9 @@ def main(argv=None):
     ap.add_argument("--env-precision", default=None, choices=["fp64", "fp32", "bf16x3"],
                     help="contractions of the ascent and the environments (default: --precision)")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--si-levels", type=int, default=1)
+    ap.add_argument("--si-levels", type=int, default=3,
+                    help="scale-invariant layers whose environments update the scale-invariant "
+                         "tensors (1 = the first layer only, which stalls near convergence)")
     ap.add_argument("--every", type=int, default=10)
     ap.add_argument("--save", default=None)
     ap.add_argument("--resume", default=None)

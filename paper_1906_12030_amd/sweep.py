@@ -174,7 +174,7 @@ def layer_dims(m: GpuMera):
 
 
 def optimize(chi: int, n_transitional: int, sweeps: int, seed=0, iters=30, precision="fp64",
-             si_levels=1, callback=None, device="cuda"):
+             si_levels=3, callback=None, device="cuda"):
     """Seeded initial state, initial fixed point, then `sweeps` sweeps; returns (state, energies)."""
     m = GpuMera.seeded(chi, n_transitional, seed, device)
     h1, shift = ops.tfim_hamiltonian(1.0, device)

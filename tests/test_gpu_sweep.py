@@ -25,10 +25,13 @@ def mods():
     return ops, sweep
 
 
-@pytest.mark.parametrize("chi,T,nsweep", [(4, 2, 12), (6, 2, 4)])
-def test_sweep_trajectory_matches_oracle(mods, chi, T, nsweep):
+@pytest.mark.parametrize("chi,T,nsweep,levels", [(4, 2, 12, 1), (6, 2, 4, 1), (4, 2, 12, 3), (6, 2, 4, 3)])
+def test_sweep_trajectory_matches_oracle(mods, chi, T, nsweep, levels):
+    """levels = number of scale-invariant layers whose environments update the
+    scale-invariant tensors (1: the first only; 3: the tower pinned by finite
+    differences in test_oracle_sweep_pins)."""
     ops, sweep = mods
-    print(f"sweep parity chi={chi} T={T}", flush=True, file=sys.stderr)
+    print(f"sweep parity chi={chi} T={T} si_levels={levels}", flush=True, file=sys.stderr)
     layers, si = I.init_mera(chi, T, 0)
     ost = O.MeraState(layers, si)
     h_o, c_o = O.shifted_hamiltonian()
@@ -39,8 +42,8 @@ def test_sweep_trajectory_matches_oracle(mods, chi, T, nsweep):
     assert abs(c_o - c_g) < 1e-14
     assert np.abs(m.rho_star.cpu().numpy() - ost.rho_star).max() < 1e-12
     for k in range(nsweep):
-        e_o = O.sweep(ost, h_o, c_o, iters=30)
-        e_g, c = sweep.sweep(m, h_g, c_g, 30, "fp64")
+        e_o = O.sweep(ost, h_o, c_o, iters=30, si_levels=levels)
+        e_g, c = sweep.sweep(m, h_g, c_g, 30, "fp64", si_levels=levels)
         e_g = float(e_g.item()) + c
         assert abs(e_g - e_o) < 1e-11, (k, e_g, e_o)
     st = m.state_dict()
