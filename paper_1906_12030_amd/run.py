@@ -31,9 +31,13 @@ from . import autograd, inputs, ops, scaling, sweep
 EXACT = -4.0 / math.pi
 
 
-def save_state(path, m: sweep.GpuMera, meta: dict):
+def save_state(path, m: sweep.GpuMera, meta: dict, with_rho=True):
+    """Tensors (and rho*, unless with_rho is False: it is chi^6 doubles and is recomputed
+    by the fixed-point iteration when such a state is resumed) as an .npz file."""
     st = m.state_dict()
-    arrays = {"rho_star": st["rho_star"], "si_u": st["si"][0], "si_w": st["si"][1]}
+    arrays = {"si_u": st["si"][0], "si_w": st["si"][1]}
+    if with_rho:
+        arrays["rho_star"] = st["rho_star"]
     for t, (u, w) in enumerate(st["layers"]):
         arrays[f"u{t}"] = u
         arrays[f"w{t}"] = w
@@ -45,7 +49,9 @@ def load_state(path, device="cuda"):
     meta = json.loads(str(z["meta"]))
     T = sum(1 for k in z.files if k.startswith("u"))
     layers = [(z[f"u{t}"], z[f"w{t}"]) for t in range(T)]
-    return sweep.GpuMera(layers, (z["si_u"], z["si_w"]), z["rho_star"], device), meta
+    rho = z["rho_star"] if "rho_star" in z.files else None
+    meta["has_rho"] = rho is not None
+    return sweep.GpuMera(layers, (z["si_u"], z["si_w"]), rho, device), meta
 
 
 def pad_with_noise(small_layers, small_si, chi, n_transitional, seed, noise=1e-3):
@@ -104,6 +110,8 @@ def main(argv=None):
                          "tensors (1 = the first layer only, which stalls near convergence)")
     ap.add_argument("--every", type=int, default=10)
     ap.add_argument("--save", default=None)
+    ap.add_argument("--save-without-rho", action="store_true",
+                    help="leave rho* out of the saved state (recomputed on --resume)")
     ap.add_argument("--resume", default=None)
     ap.add_argument("--grow-from", default=None)
     ap.add_argument("--dims", type=int, default=0)
@@ -141,7 +149,7 @@ def main(argv=None):
     else:
         m = sweep.GpuMera.seeded(a.chi, a.layers, a.seed)
     h1, shift = ops.tfim_hamiltonian(1.0)
-    if not a.resume:
+    if not a.resume or not meta.get("has_rho", True):
         sweep.initial_fixed_point(m, a.iters, a.precision)
     log = open(a.log, "a") if a.log else None
     t0 = time.perf_counter()
@@ -161,7 +169,8 @@ def main(argv=None):
                 log.flush()
     if a.save:
         save_state(a.save, m, {"sweep": start + a.sweeps, "chi": a.chi, "layers": a.layers,
-                               "seed": a.seed, "iters": a.iters, "precision": a.precision})
+                               "seed": a.seed, "iters": a.iters, "precision": a.precision},
+                   with_rho=not a.save_without_rho)
     if a.dims > 0 and not a.compare_precisions:
         d, lam, calls = scaling.scaling_dimensions(m.si[0], m.si[1], k=a.dims)
         print(json.dumps({"scaling_dimensions": [round(float(x), 6) for x in d], "matvecs": calls}), flush=True)

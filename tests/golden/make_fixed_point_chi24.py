@@ -12,7 +12,7 @@ by slice over its first fine leg (chi^7 intermediates would need 37 GB), then
     (size, NSAMPLE, replace=False), sorted.
 
 Run from the repository root:  python tests/golden/make_fixed_point_chi24.py  (one to two
-hours on 8 cores, under 16 GB of memory).
+hours on 8 cores, under 16 GB of memory; each power iteration is 48 slices of the descend).
 """
 import json
 import os
@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 from oracle import mera_oracle as O  # noqa: E402
 from paper_1906_12030_amd import inputs as I  # noqa: E402
 
-CHI, T, SEED, ITERS, SAMPLE_SEED, NSAMPLE = 24, 3, 0, 30, 12345, 2048
+CHI, T, SEED, ITERS, SAMPLE_SEED, NSAMPLE = 24, 3, 0, 8, 12345, 2048
 
 
 def main():
