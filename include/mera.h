@@ -290,8 +290,9 @@ double mera_flops(int op, int32_t din, int32_t dout, int placement);
  * env_w, or one fixed-point iteration) for these sizes, one line per
  * contraction, "la,lb->lc <kernel> m=M n=N k=K tiles=TMxTN splits=S store=..."
  * with <kernel> one of f64, f32, b3 (128 x 128 split-bf16 kernel) and b3x192
- * / b3x256 (large-tile split-bf16 kernel), and store= n4 / n1 (vector /
- * element stores along the output's n legs) or m4 / m1 (along its m legs).
+ * / b3x256 / b3x288 (large-tile split-bf16 kernel), and store= n8 (16-byte
+ * halves of whole 8-column split groups along the output's n legs), n4 / n1
+ * (vector / element stores along n) or m4 / m1 (along its m legs).
  * Writes at most out_bytes bytes (NUL-terminated) into out (host memory,
  * nullable) and the full size including the NUL into *needed (nullable).
  * The unsliced schedule, with the full workspace.  Returns MERA_EINVAL /

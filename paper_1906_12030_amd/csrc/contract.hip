@@ -443,6 +443,11 @@ hipError_t make_plan(Arith ar, const LabelDims& dims, const LabelDims& cd, const
       for (int d = 0; d < args.gn.nd - 1; ++d) nv = nv && args.gn.sy[d] % 4 == 0;
       for (int d = 0; d < args.gm.nd; ++d) nv = nv && args.gm.sy[d] % 4 == 0;
       args.cvec = nv ? 1 : 0;
+      bool g8 = args.csplit && args.gn.sy[args.gn.nd - 1] == 1 && args.gn.size[args.gn.nd - 1] % 8 == 0 &&
+                reinterpret_cast<uintptr_t>(C) % 32 == 0;
+      for (int d = 0; d < args.gn.nd - 1; ++d) g8 = g8 && args.gn.sy[d] % 8 == 0;
+      for (int d = 0; d < args.gm.nd; ++d) g8 = g8 && args.gm.sy[d] % 8 == 0;
+      args.cgroup8 = g8 ? 1 : 0;
     }
   }
   if (m_store) {
@@ -501,7 +506,7 @@ std::string contract_plan(Arith ar, const LabelDims& dims, const char* la, const
   std::snprintf(buf, sizeof(buf), "%s%s m=%lld n=%lld k=%lld tiles=%dx%d splits=%d store=%s", kern,
                 pl.use_x ? std::to_string(pl.xbn).c_str() : "", (long long)pl.M, (long long)pl.N,
                 (long long)pl.K, a.tiles_m, a.tiles_n, a.splits,
-                a.cm == 1 ? "m4" : a.cm == 2 ? "m1" : a.cvec ? "n4" : "n1");
+                a.cm == 1 ? "m4" : a.cm == 2 ? "m1" : a.cgroup8 ? "n8" : a.cvec ? "n4" : "n1");
   return buf;
 }
 

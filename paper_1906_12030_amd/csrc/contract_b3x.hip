@@ -159,6 +159,61 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[Geo<BN
     }
     return;
   }
+  if (p.cgroup8 && p.splits == 1 && alpha == 1.0 && beta == 0.0 && m0 + kBM <= (uint32_t)p.M &&
+      n0 + BN <= (uint32_t)p.N) {
+    // Whole tile inside C, plain split store along n: lane l of a wave writes the
+    // 16-byte hi (l even) or lo (l odd) half of one 8-column group of a tile row, so
+    // one store instruction of a wave covers 64 consecutive group halves of C.
+    constexpr int HALVES = BN / 4;       // group halves per tile row
+    constexpr int ROWS8 = 16 / G::kWGN;  // rows of each 16-row group written by a wave
+    constexpr int IT8 = ROWS8 * HALVES / 64;
+    static_assert(ROWS8 * HALVES % 64 == 0, "epilogue geometry");
+    const int wr8 = (wave % G::kWGN) * ROWS8;
+    const bool lo = (lane & 1) != 0;
+    __syncthreads();  // offsets staged
+    int rr[IT8], cc[IT8];
+    int64_t cb[IT8];
+#pragma unroll
+    for (int it = 0; it < IT8; ++it) {
+      const int idx = it * 64 + lane;
+      rr[it] = wr8 + idx / HALVES;
+      cc[it] = 8 * ((idx % HALVES) >> 1);
+      cb[it] = cols[cc[it]];
+    }
+    char* __restrict__ Cb = static_cast<char*>(p.c);
+#pragma unroll
+    for (int i = 0; i < G::kWMB; ++i) {
+      if (i > 0) __syncthreads();  // previous row group consumed
+#pragma unroll
+      for (int j = 0; j < G::kWNB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          st[(4 * (lane >> 4) + r) * LD + wn + j * 16 + (lane & 15)] = acc[i][j][r];
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < IT8; ++it) {
+        const float* s8 = st + rr[it] * LD + cc[it];
+        const f4_t x0 = *reinterpret_cast<const f4_t*>(s8);
+        const f4_t x1 = *reinterpret_cast<const f4_t*>(s8 + 4);
+        const int64_t ro = rows[wm + i * 16 + rr[it]];
+        u4_t w;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float a = e < 2 ? x0[2 * e] : x1[2 * e - 4];
+          const float b = e < 2 ? x0[2 * e + 1] : x1[2 * e - 3];
+          uint32_t ha = bf16_bits(a), hb = bf16_bits(b);
+          if (lo) {
+            ha = bf16_bits(a - bf16_value((uint16_t)ha));
+            hb = bf16_bits(b - bf16_value((uint16_t)hb));
+          }
+          w[e] = ha | (hb << 16);
+        }
+        // the group starts at element ro + cb (a multiple of 8): byte 4 (ro + cb)
+        *reinterpret_cast<u4_t*>(Cb + 4 * (ro + cb[it]) + (lo ? 16 : 0)) = w;
+      }
+    }
+    return;
+  }
   const bool vec = p.cvec != 0;
   // The waves of a row of waves park their 16 x kWN blocks side by side, then
   // each writes 16 / kWGN whole rows of the tile (BN contiguous columns): a
@@ -284,12 +339,12 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
   // One barrier per k-tile: after a wave's own loads of tile kt have landed
   // it waits at the barrier, which then also proves that every wave has
   // finished tile kt-1, so the loads of tile kt+1 may overwrite that stage
-  // while the MFMAs of tile kt run.
+  // while the MFMAs of tile kt run (issued after the first fragment reads of
+  // tile kt, whose LDS latency they then overlap).
   issue(0, 0);
   for (int kt = 0; kt < nk; ++kt) {
     wait_vmcnt<0>();
     barrier_nofence();
-    if (kt + 1 < nk) issue((kt + 1) & 1, kt + 1);
     const char* sa = smem + (kt & 1) * G::kStage;
     const char* sb = sa + G::kATile;
     if constexpr (G::kWMB == 8) {
@@ -309,6 +364,8 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
     };
     read_a(0, ra[0]);
     read_a(1, ra[1]);
+    // the next tile's loads go out after the first fragment reads of this one
+    if (kt + 1 < nk) issue((kt + 1) & 1, kt + 1);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       if (i + 2 < 8) read_a(i + 2, ra[(i + 2) % 3]);
@@ -341,6 +398,7 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
       };
       read_b(0, rb[0]);
       read_b(1, rb[1]);
+      if (kt + 1 < nk) issue((kt + 1) & 1, kt + 1);
 #pragma unroll
       for (int j = 0; j < G::kWNB; ++j) {
         if (j + 2 < G::kWNB) read_b(j + 2, rb[(j + 2) % 3]);
@@ -403,3 +461,4 @@ hipError_t launch_contract_b3x(const TcArgs& a, int bn, bool c_f64, hipStream_t 
 }
 
 }  // namespace mera
+

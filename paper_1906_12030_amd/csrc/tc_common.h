@@ -38,6 +38,11 @@ struct TcArgs {
   // and every other C stride a multiple of 4 (four consecutive rows form one
   // aligned vector); 2 = it is an m leg otherwise (element stores along m).
   int32_t cm;
+  // Large-tile kernel, split C stored along n: 1 when every 8-aligned group of 8
+  // consecutive output columns is one planar group of C (innermost n leg with
+  // unit stride and an extent that is a multiple of 8, every other C stride a
+  // multiple of 8), so that a lane can store the 16-byte hi or lo half of a group.
+  int32_t cgroup8;
 };
 
 // Split tensors.  The split-bf16 path keeps every FP32 value x as two bf16
@@ -93,18 +98,12 @@ __device__ __forceinline__ int64_t goff(const Group& g, uint32_t idx) {
   return off;
 }
 
-// Tile of this workgroup.  Hardware dispatches consecutive workgroups round
-// robin over the 8 XCDs, so workgroup b runs on XCD b % 8; remap so that each
-// XCD owns a contiguous range of logical tiles, then walk that range in groups
-// of group_m tile rows (column-major inside a group) so that concurrently
-// running workgroups of one XCD share A and B panels in its L2.
-__device__ __forceinline__ bool tile_of_block(const TcArgs& p, int& tm, int& tn, int& split) {
-  const int bid = blockIdx.x;
-  const int xcd = bid & 7;
-  const int idx = bid >> 3;
-  int logical = xcd * p.per_xcd + idx;
+// Tile of a logical tile index: XCD x owns the contiguous range of logical
+// tiles [x * per_xcd, (x + 1) * per_xcd), walked in groups of group_m tile rows
+// (column-major inside a group) so that concurrently running workgroups of one
+// XCD share A and B panels in its L2.
+__device__ __forceinline__ void tile_at(const TcArgs& p, int logical, int& tm, int& tn, int& split) {
   const int total = p.tiles_m * p.tiles_n;
-  if (logical >= total * p.splits) return false;
   split = logical / total;
   logical -= split * total;
   const int gsz_full = p.group_m * p.tiles_n;
@@ -114,6 +113,16 @@ __device__ __forceinline__ bool tile_of_block(const TcArgs& p, int& tm, int& tn,
   const int in_group = logical - group * gsz_full;
   tm = first_m + in_group % gsize;
   tn = in_group / gsize;
+}
+
+// Tile of this workgroup.  Hardware dispatches consecutive workgroups round
+// robin over the 8 XCDs, so workgroup b runs on XCD b % 8 and takes logical
+// tile (b % 8) * per_xcd + b / 8.
+__device__ __forceinline__ bool tile_of_block(const TcArgs& p, int& tm, int& tn, int& split) {
+  const int bid = blockIdx.x;
+  const int logical = (bid & 7) * p.per_xcd + (bid >> 3);
+  if (logical >= p.tiles_m * p.tiles_n * p.splits) return false;
+  tile_at(p, logical, tm, tn, split);
   return true;
 }
 
@@ -336,6 +345,13 @@ __device__ __forceinline__ void store_c(const TcArgs& p, TC* C, int64_t off, dou
 template <typename TC, typename X>
 __device__ __forceinline__ void store_c4(const TcArgs& p, TC* C, int64_t off, const X& x, double alpha,
                                          double beta) {
+  if constexpr (sizeof(TC) == 4) {
+    if (p.csplit && alpha == 1.0 && beta == 0.0) {  // plain store: no rescaling in double
+      const float f[4] = {(float)x[0], (float)x[1], (float)x[2], (float)x[3]};
+      split_store4(C, off, f);
+      return;
+    }
+  }
   double y[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {

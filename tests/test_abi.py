@@ -203,7 +203,7 @@ def test_schedule_plan_split_bf16_descend_on_large_tile_kernel(lib):
     iteration) is planned on the large-tile kernel, with a column tile that divides
     chi^2 = 576 where that operand is the n side (288 for the long k ranges, 192 for
     the short ones); the intermediates whose innermost leg is an m leg are stored
-    along m."""
+    along m, the two chi^7 ones (left Y and right T1) as whole 8-column split groups."""
     chi = 24
     plans = _plans(_lib.MERA_OP_DESCEND, chi, chi, _lib.MERA_BF16X3)
     big = [p for p in plans if p[2] * p[3] * p[4] >= chi ** 8]
@@ -212,7 +212,9 @@ def test_schedule_plan_split_bf16_descend_on_large_tile_kernel(lib):
         assert kern.startswith("b3x"), (labels, kern)
         if n == chi * chi:
             assert kern == ("b3x288" if k >= 2048 else "b3x192"), labels
-        assert store in ("n4", "m4"), (labels, store)
+        assert store in ("n8", "n4", "m4"), (labels, store)
+        if m * n == chi ** 7:
+            assert store == "n8", (labels, store)
     assert sum(p[5] == "m4" for p in big) >= 6
     # flops: the FP64 schedule is the one mera_flops counts; the split-bf16 one
     # forms two k-contiguous copies of X (one chi^8 contraction more)
