@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void tc_splitk_reduce(TcArgs p) {
     for (int c = 0; c < p.splits; ++c) s += p.part[c * mn + t];
     const uint32_t m = (uint32_t)(t / p.N), n = (uint32_t)(t - (int64_t)m * p.N);
     TC* C = static_cast<TC*>(p.c);
-    const int64_t off = goff<true>(p.gm, m) + goff<true>(p.gn, n);
+    const int64_t off = goff<true>(p.gm, (uint32_t)p.m_base + m) + goff<true>(p.gn, n);
     double y = p.alpha * s;
     if (p.beta != 0.0) y += p.beta * load_c(p, C, off);
     store_c(p, C, off, y);
@@ -314,6 +314,9 @@ struct Plan {
   bool A_KC = false, va = false, B_NC = false, vb = false, kal = false;
   bool use_x = false;
   int xbn = 0;
+  // large-tile launches with a short last wave: the last tail_tm tile rows run as
+  // a second launch split tail_ks ways along k (see plan_tail)
+  int tail_tm = 0, tail_ks = 0;
 };
 
 // Plans C[lc] = A[la] . B[lb].  `m_store`: C's innermost leg is an m leg,
@@ -467,6 +470,34 @@ hipError_t make_plan(Arith ar, const LabelDims& dims, const LabelDims& cd, const
 // Operand order and plan: the general kernels store along n, so C's innermost
 // leg must come from "B"; the large-tile split-bf16 kernel also stores along
 // m and then takes the operands in the given order (A = m side).
+// Tail of a large-tile launch.  When the tiles fill whole waves of the GPU's
+// workgroup slots except for a last wave that fills at most a quarter of them,
+// and the k range is long (at least 64 k-tiles), the rows of that last wave run as a second launch
+// whose tiles are split along k (at least 8 k-tiles per split) over the free
+// slots, with the partial sums reduced in a fixed order afterwards: no CU then
+// works through a whole extra tile while the others wait.  Needs scratch for the
+// partial sums of the tail rows.
+void plan_tail(Plan& pl, bool have_scratch, size_t scratch_elems) {
+  const TcArgs& a = pl.args;
+  pl.tail_tm = pl.tail_ks = 0;
+  if (!pl.use_x || a.splits != 1 || !have_scratch) return;
+  const int64_t slots = b3x_slots();
+  const int64_t tiles = (int64_t)a.tiles_m * a.tiles_n;
+  const int64_t full = tiles / slots * slots, rem = tiles - full;
+  if (full == 0 || rem == 0 || 4 * rem > slots || full % a.tiles_n != 0) return;
+  const int64_t nk = pl.K / 32;
+  if (nk < 64) return;  // short k ranges: the two extra launches would cost what they save
+  int64_t ks = std::min<int64_t>(slots / rem, nk / 8);
+  if (ks < 2) return;
+  const int64_t chunk = (nk + ks - 1) / ks;  // k-tiles per split
+  ks = (nk + chunk - 1) / chunk;
+  const int64_t tail_tm = rem / a.tiles_n;
+  const int64_t rows = pl.M - (int64_t)(a.tiles_m - tail_tm) * 256;
+  if (ks < 2 || (size_t)(ks * rows * pl.N) > scratch_elems) return;
+  pl.tail_tm = (int)tail_tm;
+  pl.tail_ks = (int)ks;
+}
+
 hipError_t choose_plan(Arith ar, const LabelDims& dims, const LabelDims& cd, const void* A,
                        const char* la_, const void* B, const char* lb_, void* C, const char* lc_,
                        bool c_f64, double alpha, double beta, double* scratch,
@@ -503,11 +534,14 @@ std::string contract_plan(Arith ar, const LabelDims& dims, const char* la, const
   char buf[160];
   const TcArgs& a = pl.args;
   const char* kern = ar == Arith::F64 ? "f64" : ar == Arith::F32 ? "f32" : pl.use_x ? "b3x" : "b3";
+  plan_tail(pl, scratch_elems > 0, scratch_elems);
   std::snprintf(buf, sizeof(buf), "%s%s m=%lld n=%lld k=%lld tiles=%dx%d splits=%d store=%s", kern,
                 pl.use_x ? std::to_string(pl.xbn).c_str() : "", (long long)pl.M, (long long)pl.N,
                 (long long)pl.K, a.tiles_m, a.tiles_n, a.splits,
                 a.cm == 1 ? "m4" : a.cm == 2 ? "m1" : a.cgroup8 ? "n8" : a.cvec ? "n4" : "n1");
-  return buf;
+  std::string out(buf);
+  if (pl.tail_tm > 0) out += " tail=" + std::to_string(pl.tail_tm) + "x" + std::to_string(pl.tail_ks);
+  return out;
 }
 
 hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* la_, const void* B,
@@ -533,7 +567,38 @@ hipError_t contract(Arith ar, const LabelDims& dims, const void* A, const char* 
     e = c64 ? dispatch<float, double>(args, blocks, pl.A_KC, pl.va, pl.B_NC, pl.vb, pl.kal, stream)
             : dispatch<float, float>(args, blocks, pl.A_KC, pl.va, pl.B_NC, pl.vb, pl.kal, stream);
   } else if (pl.use_x) {
-    e = launch_contract_b3x(args, pl.xbn, c64, stream);
+    plan_tail(pl, scratch != nullptr, scratch_elems);
+    if (pl.tail_tm == 0) {
+      e = launch_contract_b3x(args, pl.xbn, c64, stream);
+    } else {
+      // the whole waves of tiles: rows [0, head), one tile per slot and wave
+      TcArgs head = args;
+      head.tiles_m = args.tiles_m - pl.tail_tm;
+      head.M = head.tiles_m * 256;
+      head.per_xcd = (head.tiles_m * head.tiles_n + 7) / 8;
+      e = launch_contract_b3x(head, pl.xbn, c64, stream);
+      if (e != hipSuccess) return e;
+      // the tail rows, split along k into double partial sums, then reduced
+      TcArgs tail = args;
+      tail.m_base = head.M;
+      tail.M = args.M - head.M;
+      tail.tiles_m = pl.tail_tm;
+      tail.splits = pl.tail_ks;
+      tail.kchunk = (int32_t)((pl.K / 32 + pl.tail_ks - 1) / pl.tail_ks * 32);
+      tail.part = scratch;
+      tail.cvec = (tail.N % 4 == 0) ? 1 : 0;
+      tail.cgroup8 = 0;
+      tail.per_xcd = (tail.tiles_m * tail.tiles_n * tail.splits + 7) / 8;
+      e = launch_contract_b3x(tail, pl.xbn, true, stream);
+      if (e != hipSuccess) return e;
+      const int64_t tmn = (int64_t)tail.M * tail.N;
+      const int tgrid = (int)std::min<int64_t>((tmn + 255) / 256, 8192);
+      if (c_f64)
+        hipLaunchKernelGGL(tc_splitk_reduce<double>, dim3(tgrid), dim3(256), 0, stream, tail);
+      else
+        hipLaunchKernelGGL(tc_splitk_reduce<float>, dim3(tgrid), dim3(256), 0, stream, tail);
+      return hipGetLastError();
+    }
   } else {
     e = launch_contract_b3(args, pl.A_KC, pl.va, pl.B_NC, pl.vb, pl.kal, c64, stream);
   }

@@ -32,6 +32,8 @@
 //     LDS read and the MFMA.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "engine.h"
 #include "tc_common.h"
 
@@ -117,7 +119,8 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[Geo<BN
     if (i < kBM) {
       const uint32_t m = m0 + i;
       int64_t o = -1;
-      if (m < (uint32_t)p.M) o = p.splits > 1 ? ((int64_t)split * p.M + m) * p.N : goff<true>(p.gm, m);
+      if (m < (uint32_t)p.M)
+        o = p.splits > 1 ? ((int64_t)split * p.M + m) * p.N : goff<true>(p.gm, (uint32_t)p.m_base + m);
       rows[i] = o;
     } else {
       const uint32_t n = n0 + (i - kBM);
@@ -289,7 +292,7 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
     for (int q = 0; q < G::kAIns; ++q) {
       const int r = (q * 8 + wave) * 8 + rl;
       const uint32_t rr = m0 + r;
-      const int64_t ro = rr < (uint32_t)p.M ? goff<false>(p.gm, rr) : 0;
+      const int64_t ro = rr < (uint32_t)p.M ? goff<false>(p.gm, (uint32_t)p.m_base + rr) : 0;
       asrc[q] = 4 * (ro + 4 * (ph ^ swz(r)));
     }
 #pragma unroll
@@ -436,6 +439,29 @@ bool contract_b3x_fits(int64_t M, int64_t N, int64_t K, int& bn) {
   if (K >= 2048 && w288 <= (bn == 192 ? w192 : w256)) bn = 288;
   return true;
 }
+
+namespace {
+
+// Compute units of the current device, looked up once per device (256 when the
+// query fails, e.g. without a device).
+int device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 8)
+      cus = 256;
+    v = cus;
+    cache[dev].store(v, std::memory_order_relaxed);
+  }
+  return v;
+}
+
+}  // namespace
+
+int b3x_slots() { return device_cus(); }
 
 hipError_t launch_contract_b3x(const TcArgs& a, int bn, bool c_f64, hipStream_t s) {
   const int blocks = a.per_xcd * 8;

@@ -43,6 +43,9 @@ struct TcArgs {
   // unit stride and an extent that is a multiple of 8, every other C stride a
   // multiple of 8), so that a lane can store the 16-byte hi or lo half of a group.
   int32_t cgroup8;
+  // Large-tile kernel and split-k reduction: row m of this launch is row
+  // m_base + m of the contraction (a launch over the last rows only).
+  int32_t m_base;
 };
 
 // Split tensors.  The split-bf16 path keeps every FP32 value x as two bf16
@@ -132,6 +135,8 @@ hipError_t launch_contract_b3(const TcArgs& a, bool akc, bool va, bool bnc, bool
 // whether an M x N output suits it (and its column tile), and the launch.
 bool contract_b3x_fits(int64_t M, int64_t N, int64_t K, int& bn);
 hipError_t launch_contract_b3x(const TcArgs& a, int bn, bool c_f64, hipStream_t s);
+// Workgroup slots of the large-tile kernel on the current device (one per CU).
+int b3x_slots();
 
 }  // namespace mera
 

@@ -194,7 +194,7 @@ def _plans(op, d_in, d_out, prec, placement=_lib.MERA_AVG):
     for ln in lines:
         labels, kern, *rest = ln.split()
         kv = dict(x.split("=") for x in rest)
-        out.append((labels, kern, int(kv["m"]), int(kv["n"]), int(kv["k"]), kv["store"]))
+        out.append((labels, kern, int(kv["m"]), int(kv["n"]), int(kv["k"]), kv["store"], kv.get("tail")))
     return out
 
 
@@ -208,20 +208,23 @@ def test_schedule_plan_split_bf16_descend_on_large_tile_kernel(lib):
     plans = _plans(_lib.MERA_OP_DESCEND, chi, chi, _lib.MERA_BF16X3)
     big = [p for p in plans if p[2] * p[3] * p[4] >= chi ** 8]
     assert len(big) == 11  # X1, two copies of X, four chi^9 and four chi^8 chain steps
-    for labels, kern, m, n, k, store in big:
+    for labels, kern, m, n, k, store, tail in big:
         assert kern.startswith("b3x"), (labels, kern)
         if n == chi * chi:
             assert kern == ("b3x288" if k >= 2048 else "b3x192"), labels
         assert store in ("n8", "n4", "m4"), (labels, store)
         if m * n == chi ** 7:
             assert store == "n8", (labels, store)
+        # 1296 x 2 tiles of the long-k launches fill ten waves of 256 slots and an eighth
+        # of an eleventh: the last 16 tile rows run split eight ways along k
+        assert tail == ("16x8" if k == chi ** 3 else None), (labels, tail)
     assert sum(p[5] == "m4" for p in big) >= 6
     # flops: the FP64 schedule is the one mera_flops counts; the split-bf16 one
     # forms two k-contiguous copies of X (one chi^8 contraction more)
     p64 = _plans(_lib.MERA_OP_DESCEND, chi, chi, _lib.MERA_FP64)
-    f64 = sum(2.0 * m * n * k for _, _, m, n, k, _ in p64)
+    f64 = sum(2.0 * m * n * k for _, _, m, n, k, _, _ in p64)
     assert f64 == _lib.load().mera_flops(_lib.MERA_OP_DESCEND, chi, chi, _lib.MERA_AVG)
-    fb3 = sum(2.0 * m * n * k for _, _, m, n, k, _ in plans)
+    fb3 = sum(2.0 * m * n * k for _, _, m, n, k, _, _ in plans)
     assert fb3 == f64 + 2.0 * chi ** 8
     # the same steps in FP64 and FP32 keep their own kernels
     assert {p[1] for p in p64} == {"f64"}
