@@ -1,4 +1,4 @@
-"""Precision form against the FP64 oracle at chi = 16 (seeded, not optimised).
+"""Precision form against the FP64 oracle at chi = 16 and chi = 24 (seeded, not optimised).
 
 Reference values (energy, norm, purity and 512 entries of rho*) come from
 tests/golden/precision_chi16.json, written by the oracle alone.  The GPU computes
@@ -60,3 +60,40 @@ def test_precision_form_vs_oracle_chi16(mods, prec):
           flush=True, file=sys.stderr)
     be, br = BOUNDS[prec]
     assert de < be and drho < br and dfro < br and dpur < 2 * br, (de, drho, dfro, dpur)
+
+
+GOLD24 = json.load(open(os.path.join(HERE, "golden", "fixed_point_chi24.json")))
+# chi = 24, the benchmark's seeded state: bounds on |dE|, on max |drho| / max |rho| over the
+# sample and on the fixed-point residual ||D(rho) - rho|| / ||rho|| of the returned density.
+# FP64: the GPU differs from the oracle only in the order of summation; split bf16 (one
+# iterative-refinement cycle from the maximally mixed density): the |dE| <= 1e-9 bar and ten
+# times the chi = 16 density error.
+BOUNDS24 = {"fp64": (1e-12, 1e-11, 1e-12), "bf16x3": (1e-9, 5e-6, 1e-5)}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_fixed_point_and_energy_vs_oracle_chi24(mods, prec):
+    """rho* by the stored number of power iterations from the maximally mixed density, then
+    the energy by FP64 descent through the transitional layers, against the oracle's sliced
+    evaluation of the same steps (tests/golden/make_fixed_point_chi24.py)."""
+    ops, sweep = mods
+    g = GOLD24
+    r = g["recipe"]
+    print(f"fixed point chi={r['chi']} iters={r['power_iterations']} {prec}", flush=True, file=sys.stderr)
+    layers, si = I.init_mera(r["chi"], r["transitional_layers"], r["seed"])
+    m = sweep.GpuMera(layers, si)
+    h1, shift = ops.tfim_hamiltonian(1.0)
+    _, res, _ = ops.fixed_point_rho(m.si_layer(), m.rho_star, r["power_iterations"], prec, want_residual=True)
+    e = sweep.energy(m, h1, shift)
+    res = float(res.item())
+    rho = m.rho_star.reshape(-1)
+    idx = torch.tensor(g["rho_sample_index"], device=rho.device)
+    sample = rho[idx].cpu().numpy()
+    ref = np.array(g["rho_sample"])
+    drho = float(np.abs(sample - ref).max() / np.abs(ref).max())
+    dfro = abs(float(rho.norm()) - g["rho_fro"]) / g["rho_fro"]
+    de = abs(e - g["energy"])
+    print(f"  {prec}: |dE| = {de:.3e}  rho* sample {drho:.3e}  ||rho*|| {dfro:.3e}  residual {res:.3e} "
+          f"(oracle {g['residual']:.3e})", flush=True, file=sys.stderr)
+    be, br, bres = BOUNDS24[prec]
+    assert de < be and drho < br and dfro < br and res < bres, (de, drho, dfro, res)
