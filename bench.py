@@ -2,9 +2,13 @@
 
 One step = one optimisation sweep (ascend h, scale-invariant u/w updates, 30
 power iterations for rho*, transitional-layer updates, energy) on seeded
-synthetic tensors, with the contractions in split-bf16 ("mixed") precision and
-polar updates, fixed-point renormalisation and energy in FP64.  The same sweep
-in plain FP64 is timed beside it for the mixed-vs-FP64 ratio.
+synthetic tensors.  In the timed ("mixed") sweeps the fixed-point iteration runs
+on split-bf16 contractions in iterative-refinement form (--precision) and the
+ascent and environments on FP64 contractions (--env-precision); polar updates,
+renormalisation and energy are FP64.  The same sweep in plain FP64 is timed
+beside it for the mixed-vs-FP64 ratio, and the forms with FP32 environments,
+with every contraction in split bf16 and with FP32 contractions are timed once
+each with their energy difference after one sweep.
 
 Prints one JSON line (see the keys below).  Runs on one GPU only.
 """
