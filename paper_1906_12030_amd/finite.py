@@ -98,11 +98,14 @@ def sweep(m: FiniteMera, h1: torch.Tensor, shift: float, precision="fp64", disen
     rho = m.top_rho()
     for t in reversed(range(len(m.layers))):
         if disentangle:
-            m.layers[t][0] = ops.update_u(ops.env_u(m.layer(t), hs[t], rho, "avg", precision))
-            m.layers[t][1] = ops.update_w(ops.env_w(m.layer(t), hs[t], rho, "avg", precision))
+            m.layers[t][0] = ops.update_u(ops.env_u(m.layer(t), hs[t], rho, "avg", precision),
+                                          prev=m.layers[t][0])
+            m.layers[t][1] = ops.update_w(ops.env_w(m.layer(t), hs[t], rho, "avg", precision),
+                                          prev=m.layers[t][1])
             rho = ops.descend(m.layer(t), rho, "avg", "fp64")
         else:
-            m.layers[t][1] = ops.update_w(ops.tree_env_w(m.layers[t][1], hs[t], rho, "avg", precision))
+            m.layers[t][1] = ops.update_w(ops.tree_env_w(m.layers[t][1], hs[t], rho, "avg", precision),
+                                          prev=m.layers[t][1])
             rho = ops.tree_descend(m.layers[t][1], rho, "avg", "fp64")
     return float(ops.energy(h1, rho).item()) + shift
 

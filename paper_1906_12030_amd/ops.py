@@ -209,14 +209,32 @@ def polar_update(env: torch.Tensor, rows: int, cols: int, out=None, check=True, 
     return out, sv, st
 
 
-def update_u(env: torch.Tensor, check=True) -> torch.Tensor:
+# Relative weight of the previous tensor that breaks the tie of a rank-deficient environment.
+TIE_BREAK = 1e-10
+
+
+def _update(env: torch.Tensor, rows: int, cols: int, prev, check: bool) -> torch.Tensor:
+    """-U V^T of env.  When env is rank-deficient the minimiser of tr(env^T x) over isometries
+    is not unique and mera_polar_update reports MERA_ENUMERIC; with `prev` (the tensor being
+    updated) the update is then taken for env - t prev, t = TIE_BREAK ||env|| / ||prev||, which
+    selects among those minimisers (up to O(t)) the one closest to prev."""
+    out, _, st = polar_update(env, rows, cols, check=False)
+    if st == _lib.MERA_ENUMERIC and prev is not None:
+        t = TIE_BREAK * float(env.norm()) / float(prev.norm())
+        out, _, st = polar_update(env - t * prev, rows, cols, check=False)
+    if check:
+        _lib.check(st, "mera_polar_update")
+    return out
+
+
+def update_u(env: torch.Tensor, check=True, prev=None) -> torch.Tensor:
     d = env.shape[0]
-    return polar_update(env, d * d, d * d, check=check)[0]
+    return _update(env, d * d, d * d, prev, check)
 
 
-def update_w(env: torch.Tensor, check=True) -> torch.Tensor:
+def update_w(env: torch.Tensor, check=True, prev=None) -> torch.Tensor:
     din, _, dout = env.shape
-    return polar_update(env, din * din, dout, check=check)[0]
+    return _update(env, din * din, dout, prev, check)
 
 
 def fixed_point_rho(si: Layer, rho: torch.Tensor, iters: int, precision="fp64", want_residual=False,

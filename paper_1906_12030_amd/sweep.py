@@ -122,22 +122,22 @@ def sweep(m: GpuMera, h1: torch.Tensor, shift: float, iters=30, precision="fp64"
     for hk in h_si:
         e = ops.env_u(si, hk, m.rho_star, "avg", envp)
         eu = e if eu is None else eu.add_(e)
-    m.si[0] = ops.update_u(eu)
+    m.si[0] = ops.update_u(eu, prev=m.si[0])
     si = m.si_layer()
     ew = None
     for hk in h_si:
         e = ops.env_w(si, hk, m.rho_star, "avg", envp)
         ew = e if ew is None else ew.add_(e)
-    m.si[1] = ops.update_w(ew)
+    m.si[1] = ops.update_w(ew, prev=m.si[1])
     mark("si_update")
     ops.fixed_point_rho(m.si_layer(), m.rho_star, iters, precision)
     mark("fixed_point")
     rho = m.rho_star
     for t in reversed(range(len(m.layers))):
         lay = m.layer(t)
-        m.layers[t][0] = ops.update_u(ops.env_u(lay, hs[t], rho, "avg", envp))
+        m.layers[t][0] = ops.update_u(ops.env_u(lay, hs[t], rho, "avg", envp), prev=m.layers[t][0])
         lay = m.layer(t)
-        m.layers[t][1] = ops.update_w(ops.env_w(lay, hs[t], rho, "avg", envp))
+        m.layers[t][1] = ops.update_w(ops.env_w(lay, hs[t], rho, "avg", envp), prev=m.layers[t][1])
         lay = m.layer(t)
         rho = ops.descend(lay, rho, "avg", "fp64")
     mark("transitional")

@@ -146,6 +146,36 @@ def test_polar_rejects_rank_deficient(ops):
     assert np.all(host(sv) == 0.0) and np.all(host(out) == 0.0)
 
 
+def _polar_np(a):
+    uu, _, vt = np.linalg.svd(a, full_matrices=False)
+    return uu @ vt
+
+
+def test_rank_deficient_update_takes_the_minimiser_closest_to_the_previous_tensor(ops):
+    """A disentangler environment of rank 5 < 16 (as the scale-invariant Env_u of an optimised
+    chi = 16 state, 107 of its 256 singular values below 1e-12 of the largest): every
+    isometry -U_r V_r^T + W, W an isometry between the two null spaces, minimises
+    tr(env^T x).  With the previous tensor the update returns the one whose null-space part is
+    the polar factor of the previous tensor's null-space block (LAPACK as the comparator)."""
+    rng = np.random.default_rng(11)
+    d, r = 4, 5
+    n = d * d
+    env = rng.standard_normal((n, r)) @ rng.standard_normal((r, n))
+    prev = _polar_np(rng.standard_normal((n, n)))
+    with pytest.raises(Exception):
+        ops.update_u(gpu(env.reshape(d, d, d, d)))
+    x = host(ops.update_u(gpu(env.reshape(d, d, d, d)), prev=gpu(prev.reshape(d, d, d, d)))).reshape(n, n)
+    assert np.abs(x.T @ x - np.eye(n)).max() < 1e-12
+    uu, s, vt = np.linalg.svd(env)
+    assert abs(np.sum(env * x) + s.sum()) < 1e-9 * s.sum()
+    nl, nr = uu[:, r:], vt[r:].T
+    expected = -uu[:, :r] @ vt[:r] + nl @ _polar_np(nl.T @ prev @ nr) @ nr.T
+    # the zero singular values of env are ~3e-15 |env| after rounding, against the tie-break's
+    # 1e-10 |env|: the selected completion differs from the exact one by ~1e-6 (numpy, seeds
+    # 11..20: 7.6e-7 .. 5.3e-6)
+    assert np.abs(x - expected).max() < 2e-5
+
+
 @pytest.mark.parametrize("d", [2, 3, 4])
 def test_fixed_point(ops, d):
     rng = np.random.default_rng(40 + d)
