@@ -5,6 +5,8 @@ follow the same update order; per-sweep energies and the final tensors must
 agree to FP64 rounding (the polar updates differ only in method: SVD on the
 host vs a Newton-Schulz iteration on the device).
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -15,6 +17,9 @@ from oracle import mera_oracle as O
 from paper_1906_12030_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
+
+
+TRAJ = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "trajectories.json")
 
 
 @pytest.fixture(scope="module")
@@ -114,3 +119,33 @@ def test_checkpoint_resume_reproduces_trajectory(mods, tmp_path):
     assert meta["sweep"] == 2
     e_b += [float(sweep.sweep(b2, h, c, 30)[0].item()) for _ in range(2)]
     assert e_a == e_b
+
+
+def _stored_runs():
+    return json.load(open(TRAJ))["runs"]
+
+
+@pytest.mark.parametrize("run", range(4), ids=["chi4-seed0", "chi4-seed1", "chi4-seed2", "chi8-seed0"])
+def test_long_trajectories_match_stored_oracle_energies(mods, run):
+    """The GPU's FP64 optimisation against per-sweep energies the oracle wrote
+    (tests/golden/make_trajectories.py): chi = 4 (T = 2) for seeds 0, 1, 2 over 100 sweeps and
+    chi = 8 (T = 3) over 500 sweeps, one scale-invariant level, 30 power iterations.  Both
+    sides round differently (SVD against Newton-Schulz polar factors, other summation
+    orders), and over hundreds of sweeps such differences can grow along directions the
+    energy hardly sees; the energies are compared to 1e-10 absolute (the metric's |dE|
+    bar is 1e-9)."""
+    ops, sweep = mods
+    r = _stored_runs()[run]
+    chi, T, seed, n = r["chi"], r["transitional_layers"], r["seed"], r["sweeps"]
+    print(f"long trajectory chi={chi} T={T} seed={seed} sweeps={n}", flush=True, file=sys.stderr)
+    layers, si = I.init_mera(chi, T, seed)
+    m = sweep.GpuMera(layers, si)
+    h, c = ops.tfim_hamiltonian(1.0)
+    sweep.initial_fixed_point(m, 30, "fp64")
+    worst = 0.0
+    for k, e_o in enumerate(r["energies"]):
+        e_g, cc = sweep.sweep(m, h, c, 30, "fp64", si_levels=1)
+        d = abs(float(e_g.item()) + cc - e_o)
+        worst = max(worst, d)
+        assert d < 1e-10, (k + 1, d)
+    print(f"  largest |dE| over {n} sweeps: {worst:.3e}", flush=True, file=sys.stderr)
