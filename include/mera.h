@@ -291,8 +291,9 @@ double mera_flops(int op, int32_t din, int32_t dout, int placement);
  * contraction, "la,lb->lc <kernel> m=M n=N k=K tiles=TMxTN splits=S store=..."
  * with <kernel> one of f64, f32, b3 (128 x 128 split-bf16 kernel) and b3x192
  * / b3x256 / b3x288 (large-tile split-bf16 kernel), and store= n8 (16-byte
- * halves of whole 8-column split groups along the output's n legs), n4 / n1
- * (vector / element stores along n) or m4 / m1 (along its m legs), and for a
+ * halves of whole 8-column split groups along the output's n legs), n4 / n2 /
+ * n1 (vector / FP64 pair / element stores along n) or m4 / m1 (along its m
+ * legs), and for a
  * large-tile contraction whose last wave of tiles fills at most a quarter of
  * the GPU, tail=RxS: its last R tile rows run as a second launch split S ways
  * along k (partial sums reduced in a fixed order).

@@ -435,6 +435,13 @@ hipError_t make_plan(Arith ar, const LabelDims& dims, const LabelDims& cd, const
                  reinterpret_cast<uintptr_t>(C) % 16 == 0)
                     ? 1
                     : 0;
+  if (splits == 1) {
+    bool v2 = args.gn.sy[args.gn.nd - 1] == 1 && args.gn.size[args.gn.nd - 1] % 2 == 0 &&
+              reinterpret_cast<uintptr_t>(C) % 16 == 0;
+    for (int d = 0; d < args.gn.nd - 1; ++d) v2 = v2 && args.gn.sy[d] % 2 == 0;
+    for (int d = 0; d < args.gm.nd; ++d) v2 = v2 && args.gm.sy[d] % 2 == 0;
+    args.cvec2 = v2 ? 1 : 0;
+  }
   if (pl.use_x) {
     // the large-tile kernel stores 4 consecutive columns (a multiple of 4
     // from the tile start) as one vector
@@ -538,7 +545,8 @@ std::string contract_plan(Arith ar, const LabelDims& dims, const char* la, const
   std::snprintf(buf, sizeof(buf), "%s%s m=%lld n=%lld k=%lld tiles=%dx%d splits=%d store=%s", kern,
                 pl.use_x ? std::to_string(pl.xbn).c_str() : "", (long long)pl.M, (long long)pl.N,
                 (long long)pl.K, a.tiles_m, a.tiles_n, a.splits,
-                a.cm == 1 ? "m4" : a.cm == 2 ? "m1" : a.cgroup8 ? "n8" : a.cvec ? "n4" : "n1");
+                a.cm == 1 ? "m4" : a.cm == 2 ? "m1" : a.cgroup8 ? "n8" : a.cvec ? "n4"
+                : (a.cvec2 && ar == Arith::F64) ? "n2" : "n1");
   std::string out(buf);
   if (pl.tail_tm > 0) out += " tail=" + std::to_string(pl.tail_tm) + "x" + std::to_string(pl.tail_ks);
   return out;

@@ -46,6 +46,10 @@ struct TcArgs {
   // Large-tile kernel and split-k reduction: row m of this launch is row
   // m_base + m of the contraction (a launch over the last rows only).
   int32_t m_base;
+  // 128 x 128 kernels: every 2-aligned pair of consecutive output columns is
+  // adjacent in C (innermost n leg with unit stride and an even extent, every
+  // other C stride even, C 16-byte aligned): one 16-byte store per two doubles.
+  int32_t cvec2;
 };
 
 // Split tensors.  The split-bf16 path keeps every FP32 value x as two bf16
@@ -404,6 +408,36 @@ __device__ __forceinline__ void write_tile(const TcArgs& p, ACC (&acc)[4][4], ui
   const double alpha = p.splits > 1 ? 1.0 : p.alpha;
   const double beta = p.splits > 1 ? 0.0 : p.beta;
   const bool vec = p.cvec != 0;
+  if constexpr (VA == 2) {
+    static_assert(sizeof(TC) == 8, "double accumulators store to a double C");
+    if (p.splits == 1 && alpha == 1.0 && beta == 0.0 && (vec || p.cvec2) && m0 + 128 <= (uint32_t)p.M &&
+        n0 + 128 <= (uint32_t)p.N) {
+      // Whole tile inside C, plain store: lane l writes columns 2 (l % 32) and
+      // 2 (l % 32) + 1 of rows 2 it + l / 32 of each 16-row group, one 16-byte
+      // store per pair, with no rescaling and no per-element offset lookups.
+      const int col = (lane & 31) * 2;
+      __syncthreads();  // offsets staged
+      const int64_t co = cols[wn + col];
+      typedef AT vt __attribute__((ext_vector_type(2)));
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i > 0) __syncthreads();  // previous row group consumed
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) st[rowf(lane, r) * LD + j * 16 + (lane & 15)] = (AT)acc[i][j][r];
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          const int row = 2 * it + (lane >> 5);
+          const int64_t ro = rows[wm + i * 16 + row];
+          const vt x = *reinterpret_cast<const vt*>(&st[row * LD + col]);
+          *reinterpret_cast<vt*>(C + ro + co) = x;
+        }
+      }
+      return;
+    }
+  }
   // unrolled: acc must stay in registers (a runtime index would demote it to scratch)
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
