@@ -1,8 +1,9 @@
 """ctypes binding of libmera.so (include/mera.h).
 
 Argument marshalling only: every numerical step runs in the HIP library.  The
-library is loaded from this package directory; if it is missing, importing the
-binding raises instead of falling back to anything else.
+library is loaded from this package directory (or from the path in the environment
+variable MERA_LIBRARY, e.g. the sanitizer build); if it is missing, loading it raises
+instead of falling back to anything else.
 """
 from __future__ import annotations
 
@@ -10,7 +11,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmera.so")
+LIB_PATH = os.environ.get("MERA_LIBRARY") or os.path.join(HERE, "libmera.so")
 
 MERA_OK, MERA_EINVAL, MERA_ESHAPE, MERA_EWORKSPACE, MERA_EDEVICE, MERA_ENUMERIC, MERA_ENOTCONV = range(7)
 MERA_LEFT, MERA_RIGHT, MERA_AVG = 0, 1, 2

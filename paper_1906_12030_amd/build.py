@@ -27,20 +27,32 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    objdir = os.path.join(HERE, "_build")
+# Host-side sanitizers for the CPU checks of the planner, argument checks and sizing code
+# (libmera_asan.so; never loaded on a GPU: the device code is built without them).
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer"]
+LIB_ASAN = os.path.join(HERE, "libmera_asan.so")
+
+
+def build(verbose: bool = False, jobs: int = 8, sanitize: bool = False, out_dir: str | None = None) -> str:
+    """Compile every source and link the library; returns its path.
+
+    `sanitize` builds the host code with AddressSanitizer and UBSan (libmera_asan.so);
+    `out_dir` puts the objects and the library there instead of the package directory.
+    """
+    lib = LIB_ASAN if sanitize else LIB
+    objdir = os.path.join(HERE, "_build_asan" if sanitize else "_build")
+    if out_dir is not None:
+        lib = os.path.join(out_dir, os.path.basename(lib))
+        objdir = os.path.join(out_dir, os.path.basename(objdir))
     os.makedirs(objdir, exist_ok=True)
-    procs = []
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        objs.append(obj)
-        cmd = [hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    extra = SANITIZE_FLAGS if sanitize else []
+    objs = [os.path.join(objdir, src.replace(".hip", ".o")) for src in SOURCES]
+    pending = list(zip(SOURCES, objs))
+    running = []
     failed = []
-    for src, p in procs:
+
+    def finish(src, p):
         out, _ = p.communicate()
         lines = [ln for ln in out.splitlines() if "packed-fp32-ops" not in ln]
         if p.returncode != 0:
@@ -48,14 +60,26 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             print("\n".join(lines), file=sys.stderr)
         elif verbose and lines:
             print("\n".join(lines))
+
+    # at most `jobs` compilers at a time
+    while pending or running:
+        while pending and len(running) < max(1, jobs):
+            src, obj = pending.pop(0)
+            cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            running.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                                  text=True)))
+        finish(*running.pop(0))
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    tmp = lib + ".tmp"
+    link = ["-shared-libsan", *extra] if sanitize else []
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *link, *objs, "-o", tmp]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

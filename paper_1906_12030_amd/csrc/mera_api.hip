@@ -52,10 +52,10 @@ void set_err(const std::string& s) { g_last_error = s; }
 
 struct ProfRec {
   std::string step;
-  int arith;
-  int op;
-  double flops;
-  hipEvent_t a, b;
+  int arith = 0;
+  int op = 0;
+  double flops = 0.0;
+  hipEvent_t a = nullptr, b = nullptr;
 };
 thread_local bool g_prof_on = false;
 thread_local std::vector<ProfRec> g_prof;
@@ -117,18 +117,26 @@ struct Ctx {
       rec.arith = (int)ar;
       rec.op = g_prof_op;
       rec.flops = mera::contract_flops(dims, la, lb, lc);
-      if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) {
+      if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess ||
+          hipEventRecord(rec.a, s) != hipSuccess) {
+        if (rec.a) (void)hipEventDestroy(rec.a);
+        if (rec.b) (void)hipEventDestroy(rec.b);
         err = hipErrorOutOfMemory;
         set_err("profile event creation failed");
         return;
       }
-      hipEventRecord(rec.a, s);
     }
     err = mera::contract(ar, dims, A, la, B, lb, C, lc, cf, alpha, beta, s, &flops, scratch,
                          scratch_elems, cdims);
     if (g_prof_on) {
-      hipEventRecord(rec.b, s);
-      g_prof.push_back(rec);
+      if (hipEventRecord(rec.b, s) == hipSuccess) {
+        g_prof.push_back(rec);
+      } else {
+        (void)hipEventDestroy(rec.a);
+        (void)hipEventDestroy(rec.b);
+        if (err == hipSuccess) err = hipErrorInvalidHandle;
+        set_err("profile event record failed");
+      }
     }
     if (err != hipSuccess)
       set_err(std::string("contract ") + la + "," + lb + "->" + lc + ": " + hipGetErrorString(err));
@@ -146,6 +154,16 @@ int64_t ipow(int64_t b, int e) {
   int64_t r = 1;
   while (e-- > 0) r *= b;
   return r;
+}
+
+// p + n, for buffers that are null in the measuring pass (which takes no
+// workspace memory): an offset from a null pointer stays null.
+template <class T>
+T* advance(T* p, int64_t n) {
+  return p ? p + n : nullptr;
+}
+const void* byte_offset(const void* p, int64_t bytes) {
+  return advance(static_cast<const char*>(p), bytes);
 }
 
 // Layer tensors in the working type (converted copies for F32; split tensors for B3).
@@ -324,11 +342,11 @@ int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_
     for (int64_t r0 = 0; r0 < din; r0 += R) {
       cx.dims = full;
       cx.dims.d['r'] = std::min(R, din - r0);
-      const char* n_s = static_cast<const char*>(pc.N) + r0 * ipow(din, 3) * dout * es;  // N[r0, ...]
+      const void* n_s = byte_offset(pc.N, r0 * ipow(din, 3) * dout * es);  // N[r0, ...]
       cx.c(n_s, "rsbdj", xc.l, xc.xl, b.big, "rsbaADJ", false, 1.0, 0.0);
       cx.c(b.big, "rsbaADJ", pc.N, "RsBDJ", b.mid, mid_l, false, 1.0, 0.0);
       cx.c(b.mid, mid_l, t.u, "pqab", b.mid2, mid2_l, false, 1.0, 0.0);
-      cx.c(b.mid2, mid2_l, t.u, "PQAB", rho_out + r0 * ipow(din, 3), "pqrPQR", true, wgt, 0.0, &full);
+      cx.c(b.mid2, mid2_l, t.u, "PQAB", advance(rho_out, r0 * ipow(din, 3)), "pqrPQR", true, wgt, 0.0, &full);
     }
     cx.dims = full;
     first = false;
@@ -337,11 +355,11 @@ int run_descend(Ctx& cx, const mera_layer* L, const double* rho_in, double* rho_
     for (int64_t q0 = 0; q0 < din; q0 += R) {
       cx.dims = full;
       cx.dims.d['q'] = std::min(R, din - q0);
-      const char* m_s = static_cast<const char*>(pc.M1) + q0 * ipow(din, 3) * dout * es;  // M1[q0, ...]
+      const void* m_s = byte_offset(pc.M1, q0 * ipow(din, 3) * dout * es);  // M1[q0, ...]
       cx.c(m_s, "qpcja", xc.r, xc.xr, b.big, "pqcdDAJ", false, 1.0, 0.0);
       cx.c(b.big, "pqcdDAJ", pc.M, "pQCAJ", b.mid, mid_r, false, 1.0, 0.0);
       cx.c(b.mid, mid_r, t.u, "rscd", b.mid2, mid2_r, false, 1.0, 0.0);
-      cx.c(b.mid2, mid2_r, t.u, "RSCD", rho_out + q0 * ipow(din, 5), "qrsQRS", true, wgt,
+      cx.c(b.mid2, mid2_r, t.u, "RSCD", advance(rho_out, q0 * ipow(din, 5)), "qrsQRS", true, wgt,
            first ? 0.0 : 1.0, &full);
     }
     cx.dims = full;
@@ -882,8 +900,8 @@ const char* mera_last_error(void) { return g_last_error.c_str(); }
 
 int mera_profile_begin(void) {
   for (auto& r : g_prof) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
   g_prof.clear();
   g_prof_on = true;
@@ -909,8 +927,8 @@ int mera_profile_end(mera_profile_entry* out, int32_t max_entries, int32_t* n_ou
       out[n].ms = ms;
       ++n;
     }
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
   g_prof.clear();
   if (n_out) *n_out = n;
@@ -1029,8 +1047,8 @@ int mera_mfma_peak(int kind, void* scratch_d, size_t scratch_bytes, double* tflo
       best = ms;
     }
   }
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   if (rc == MERA_OK) {
     const double flops = (double)kBlocks * 4 * iters * mera::mfma_peak_flops_per_wave_iter(kind);
     *tflops_out = flops / (best * 1e-3) / 1e12;

@@ -266,3 +266,26 @@ def test_tree_calls_checks_and_cost(lib):
         assert all(3.5 < x < 8 for x in r), (op, r)
         assert r[2] < r[1] < r[0]  # lower orders fade
     assert _lib.mera_flops(_lib.MERA_OP_TREE_DESCEND, 24, 24, 2) < 1e-2 * _lib.mera_flops(_lib.MERA_OP_DESCEND, 24, 24, 2)
+
+
+def test_every_schedule_is_planned_and_sized(lib):
+    """The measuring pass of every call, arithmetic, placement and a range of bond
+    dimensions (ragged and sliced shapes included) returns a plan and a workspace size;
+    the sliced minimum never exceeds the full size."""
+    ops = (_lib.MERA_OP_ASCEND, _lib.MERA_OP_DESCEND, _lib.MERA_OP_ENV_U, _lib.MERA_OP_ENV_W,
+           _lib.MERA_OP_FIXED_POINT, _lib.MERA_OP_TREE_ASCEND, _lib.MERA_OP_TREE_DESCEND,
+           _lib.MERA_OP_TREE_ENV_W)
+    n = 0
+    for op in ops:
+        for prec in (_lib.MERA_FP64, _lib.MERA_FP32, _lib.MERA_BF16X3):
+            for din, dout in ((2, 2), (3, 2), (4, 3), (6, 6), (8, 8), (12, 12), (16, 16), (24, 24)):
+                for pl in (_lib.MERA_LEFT, _lib.MERA_RIGHT, _lib.MERA_AVG):
+                    if op == _lib.MERA_OP_FIXED_POINT and din != dout:
+                        continue
+                    st, plan = _lib.mera_schedule_plan(op, din, dout, prec, pl)
+                    assert st == _lib.MERA_OK and plan, (op, prec, din, dout, pl)
+                    full = _lib.mera_workspace_bytes(op, din, dout, prec, pl)
+                    least = _lib.mera_workspace_bytes_min(op, din, dout, prec, pl)
+                    assert 0 < least <= full, (op, prec, din, dout, pl, least, full)
+                    n += 1
+    assert n > 500
