@@ -7,10 +7,16 @@
 //   * 256 x BN output tile, 512 threads = 8 waves on v_mfma_f32_16x16x32_bf16:
 //     BN = 192 or 256 in a 2 (m) x 4 (n) wave grid (each wave 128 x BN/4,
 //     its B fragments held for the k-tile and its A fragments streamed
-//     through a ring of three), BN = 288 in a 4 x 2 grid (each wave 64 x 144,
+//     through a ring of four), BN = 288 in a 4 x 2 grid (each wave 64 x 144,
 //     A fragments held, B fragments streamed; 21 % fewer LDS bytes per flop
 //     than 256 x 192); twice the tile edge of the 128 x 128 kernel halves the
 //     bytes that have to come through L2 per flop;
+//   * the order of fragment reads, loads and MFMAs after each k-tile's barrier
+//     is fixed with scheduling groups: streamed fragments are read in pairs of
+//     blocks, right after the wait for the previous pair, so that each wait
+//     has 23 MFMAs of cover (the LDS-DMA loads in the loop make the compiler
+//     wait for all outstanding LDS reads at every wait, so the reads must be
+//     issued early rather than counted);
 //   * operand k-tiles (32 split elements, 128 bytes, per row) go straight
 //     from global memory into LDS with global_load_lds_dwordx4, in a two-stage ring
 //     with one barrier per k-tile: the loads of tile kt+1 fly while the
@@ -91,10 +97,29 @@ struct Geo {
   static_assert(kWN % 16 == 0 && BN % 8 == 0, "tile width");
 };
 
-// LDS bytes of the kernel: two stages, reused by the epilogue.
+// LDS bytes of the kernel: two stages, reused by the epilogue, and a junk
+// kilobyte for the DMA instructions that have no chunk of a tile to load.
 template <int BN>
 constexpr int lds_bytes() {
-  return 2 * Geo<BN>::kStage;
+  return 2 * Geo<BN>::kStage + (Geo<BN>::kBChunks % 8 == 0 ? 0 : 1024);
+}
+
+// sched_group_barrier masks: MFMA, VMEM read, LDS read
+constexpr int kSgMfma = 0x008, kSgVmem = 0x020, kSgDsRead = 0x100;
+
+// Scheduling groups of the streamed blocks J, J+1 (of NB, PER MFMAs each): the
+// first MFMA of block J (before it, the wait for the fragments of J and J+1),
+// the fragment reads of blocks J+2 and J+3, then the other MFMAs of J and J+1,
+// which give those reads time to land before the next pair's wait.
+template <int J, int NB, int PER>
+__device__ __forceinline__ void pin_pairs() {
+  if constexpr (J < NB) {
+    constexpr int ahead = J + 3 < NB ? 2 : J + 2 < NB ? 1 : 0;
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 0);
+    if constexpr (ahead > 0) __builtin_amdgcn_sched_group_barrier(kSgDsRead, 2 * ahead, 0);
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, PER * (J + 1 < NB ? 2 : 1) - 1, 0);
+    pin_pairs<J + 2, NB, PER>();
+  }
 }
 
 // Epilogue: when C is contiguous along n, each wave parks one 16-row group of
@@ -305,20 +330,22 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
   }
   KWalk<kBK> kw;
   kw.init(p.gk, kbeg);
-  auto issue = [&](int stage, int kt) {
-    if (kt > 0) kw.next();
+  // B chunks past the tile (BN = 288: 36 chunks, the fifth instruction of waves
+  // 4-7) are loaded into a junk kilobyte behind the stages, so that every wave
+  // issues the same instructions and the loop body stays one basic block.
+  auto issue = [&](int stage, int64_t ka, int64_t kb) {
     char* sa = smem + stage * G::kStage;
     char* sb = sa + G::kATile;
-    const int64_t ka = 4 * kw.oa, kb = 4 * kw.ob;
 #pragma unroll
     for (int q = 0; q < G::kAIns; ++q)
       __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(A + asrc[q] + ka),
                                        sa + (q * 8 + wave) * 1024, 16, 0, 0);
 #pragma unroll
-    for (int q = 0; q < G::kBIns; ++q)
-      if (G::kBChunks % 8 == 0 || q * 8 + wave < G::kBChunks)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(B + bsrc[q] + kb),
-                                         sb + (q * 8 + wave) * 1024, 16, 0, 0);
+    for (int q = 0; q < G::kBIns; ++q) {
+      const int c = q * 8 + wave;
+      char* dst = (G::kBChunks % 8 == 0 || c < G::kBChunks) ? sb + c * 1024 : smem + 2 * G::kStage;
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(B + bsrc[q] + kb), dst, 16, 0, 0);
+    }
   };
 
   f4_t acc[G::kWMB][G::kWNB];
@@ -333,92 +360,100 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
   const int x0 = ((2 * kq) ^ sw) << 4, x1 = ((2 * kq + 1) ^ sw) << 4;
   const int abase = (wm + lr) * kRowBytes, bbase = (wn + lr) * kRowBytes;
 
-  // the two slots of a lane are the hi and the lo halves of its 8 elements
-  auto split8 = [](const u4_t& w0, const u4_t& w1, bf8_t& hi, bf8_t& lo) {
-    hi = __builtin_bit_cast(bf8_t, w0);
-    lo = __builtin_bit_cast(bf8_t, w1);
-  };
-
-  // One barrier per k-tile: after a wave's own loads of tile kt have landed
-  // it waits at the barrier, which then also proves that every wave has
-  // finished tile kt-1, so the loads of tile kt+1 may overwrite that stage
-  // while the MFMAs of tile kt run (issued after the first fragment reads of
-  // tile kt, whose LDS latency they then overlap).
-  issue(0, 0);
+  // One barrier per k-tile: after a wave's own loads of tile kt have landed it
+  // waits at the barrier, which then also proves that every wave has finished
+  // tile kt-1, so the loads of tile kt+1 may overwrite that stage while the
+  // MFMAs of tile kt run.  The k offsets of tile kt+1 are computed before the
+  // barrier, and the last tile reloads its own (in-bounds) k range into the
+  // free stage, so everything after the barrier is branch-free; the order of
+  // the fragment reads, the loads and the MFMAs there is fixed by scheduling
+  // groups: the held fragments and the first two streamed blocks, the loads
+  // of tile kt+1, then pairs of streamed blocks, each pair's first MFMA
+  // followed by the reads of the next pair (pin_pairs).
+  issue(0, 4 * kw.oa, 4 * kw.ob);
   for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) kw.next();
+    const int64_t ka = 4 * kw.oa, kb = 4 * kw.ob;
     wait_vmcnt<0>();
     barrier_nofence();
     const char* sa = smem + (kt & 1) * G::kStage;
     const char* sb = sa + G::kATile;
-    if constexpr (G::kWMB == 8) {
-    bf8_t bh[G::kWNB], bl[G::kWNB];
-#pragma unroll
-    for (int j = 0; j < G::kWNB; ++j) {
-      const u4_t w0 = *reinterpret_cast<const u4_t*>(sb + bbase + j * 16 * kRowBytes + x0);
-      const u4_t w1 = *reinterpret_cast<const u4_t*>(sb + bbase + j * 16 * kRowBytes + x1);
-      split8(w0, w1, bh[j], bl[j]);
-    }
-    // A fragments through a ring of three: the reads of block i+2 are in
-    // flight while block i's MFMAs run
-    u4_t ra[3][2];
-    auto read_a = [&](int i, u4_t (&r)[2]) {
-      r[0] = *reinterpret_cast<const u4_t*>(sa + abase + i * 16 * kRowBytes + x0);
-      r[1] = *reinterpret_cast<const u4_t*>(sa + abase + i * 16 * kRowBytes + x1);
+    // a lane's two slots of a 16-row block: the hi and the lo halves of its 8
+    // elements, i.e. the two bf16x8 MFMA operands
+    auto rd = [&](const char* base, int row16, u4_t (&r)[2]) {
+      r[0] = *reinterpret_cast<const u4_t*>(base + row16 * 16 * kRowBytes + x0);
+      r[1] = *reinterpret_cast<const u4_t*>(base + row16 * 16 * kRowBytes + x1);
     };
-    read_a(0, ra[0]);
-    read_a(1, ra[1]);
-    // the next tile's loads go out after the first fragment reads of this one
-    if (kt + 1 < nk) issue((kt + 1) & 1, kt + 1);
+    if constexpr (G::kWMB == 8) {
+      // 2 x 4 (or 2 x 3) waves: B fragments held for the k-tile, A fragments
+      // streamed through a ring of four, read two blocks ahead
+      u4_t ra[4][2], rb[G::kWNB][2];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      if (i + 2 < 8) read_a(i + 2, ra[(i + 2) % 3]);
-      bf8_t ah, al;
-      split8(ra[i % 3][0], ra[i % 3][1], ah, al);
+      for (int j = 0; j < G::kWNB; ++j) rd(sb + bbase, j, rb[j]);
+      rd(sa + abase, 0, ra[0]);
+      rd(sa + abase, 1, ra[1]);
+      issue((kt + 1) & 1, ka, kb);
 #pragma unroll
-      for (int j = 0; j < G::kWNB; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < 8; ++i) {
+        if (i % 2 == 0 && i + 2 < 8) {
+          rd(sa + abase, i + 2, ra[(i + 2) % 4]);
+          rd(sa + abase, i + 3, ra[(i + 3) % 4]);
+        }
+        const bf8_t ah = __builtin_bit_cast(bf8_t, ra[i % 4][0]);
+        const bf8_t al = __builtin_bit_cast(bf8_t, ra[i % 4][1]);
 #pragma unroll
-      for (int j = 0; j < G::kWNB; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < G::kWNB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, __builtin_bit_cast(bf8_t, rb[j][0]),
+                                                            acc[i][j], 0, 0, 0);
 #pragma unroll
-      for (int j = 0; j < G::kWNB; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-    }
-      } else {
-      // 4 x 2 wave grid: all A fragments of the wave in registers, B
-      // fragments through a ring of three
-      bf8_t ah[G::kWMB], al[G::kWMB];
+        for (int j = 0; j < G::kWNB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf8_t, rb[j][1]),
+                                                            acc[i][j], 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < G::kWMB; ++i) {
-        const u4_t w0 = *reinterpret_cast<const u4_t*>(sa + abase + i * 16 * kRowBytes + x0);
-        const u4_t w1 = *reinterpret_cast<const u4_t*>(sa + abase + i * 16 * kRowBytes + x1);
-        split8(w0, w1, ah[i], al[i]);
+        for (int j = 0; j < G::kWNB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf8_t, rb[j][0]),
+                                                            acc[i][j], 0, 0, 0);
       }
-      u4_t rb[3][2];
-      auto read_b = [&](int j, u4_t (&r)[2]) {
-        r[0] = *reinterpret_cast<const u4_t*>(sb + bbase + j * 16 * kRowBytes + x0);
-        r[1] = *reinterpret_cast<const u4_t*>(sb + bbase + j * 16 * kRowBytes + x1);
-      };
-      read_b(0, rb[0]);
-      read_b(1, rb[1]);
-      if (kt + 1 < nk) issue((kt + 1) & 1, kt + 1);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 2 * G::kWNB + 4, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgVmem, G::kAIns + G::kBIns, 0);
+      pin_pairs<0, 8, 3 * G::kWNB>();
+    } else {
+      // 4 x 2 waves: A fragments held for the k-tile, B fragments streamed
+      // through a ring of four, read two blocks ahead
+      constexpr int NB = G::kWNB;
+      u4_t ra[G::kWMB][2], rb[4][2];
 #pragma unroll
-      for (int j = 0; j < G::kWNB; ++j) {
-        if (j + 2 < G::kWNB) read_b(j + 2, rb[(j + 2) % 3]);
-        bf8_t bh, bl;
-        split8(rb[j % 3][0], rb[j % 3][1], bh, bl);
+      for (int i = 0; i < G::kWMB; ++i) rd(sa + abase, i, ra[i]);
+      rd(sb + bbase, 0, rb[0]);
+      rd(sb + bbase, 1, rb[1]);
+      issue((kt + 1) & 1, ka, kb);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j % 2 == 0) {
+          if (j + 2 < NB) rd(sb + bbase, j + 2, rb[(j + 2) % 4]);
+          if (j + 3 < NB) rd(sb + bbase, j + 3, rb[(j + 3) % 4]);
+        }
+        const bf8_t bh = __builtin_bit_cast(bf8_t, rb[j % 4][0]);
+        const bf8_t bl = __builtin_bit_cast(bf8_t, rb[j % 4][1]);
 #pragma unroll
         for (int i = 0; i < G::kWMB; ++i)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, ra[i][1]), bh,
+                                                            acc[i][j], 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < G::kWMB; ++i)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, ra[i][0]), bl,
+                                                            acc[i][j], 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < G::kWMB; ++i)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, ra[i][0]), bh,
+                                                            acc[i][j], 0, 0, 0);
       }
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 2 * G::kWMB + 4, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgVmem, G::kAIns + G::kBIns, 0);
+      pin_pairs<0, NB, 3 * G::kWMB>();
     }
   }
+  wait_vmcnt<0>();    // the last tile's reload has landed
   barrier_nofence();  // the epilogue reuses the stages
 
   write_tile_x<TC, BN>(p, acc, m0, n0, split, smem, wm, wn);
