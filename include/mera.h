@@ -78,7 +78,8 @@ typedef enum {
   MERA_OP_ENERGY = 6,
   MERA_OP_TREE_ASCEND = 7,   /* binary tree network calls (mera_tree_*) */
   MERA_OP_TREE_DESCEND = 8,
-  MERA_OP_TREE_ENV_W = 9
+  MERA_OP_TREE_ENV_W = 9,
+  MERA_OP_POLAR_NEAR = 10   /* mera_polar_update_near; din = rows, dout = cols */
 } mera_op;
 
 /* One MERA layer: disentangler u (din^4) and isometry w (din*din*dout), both
@@ -153,6 +154,26 @@ int mera_env_w(const mera_layer* layer, const double* h_d, const double* rho_d, 
 int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* out_d, double* sv_d,
                       void* ws_d, size_t ws_bytes, void* hip_stream);
 
+/* SVD update (Sec. II.C, Fig. 5) that stays defined for a rank-deficient
+ * environment.  The paper's update minimises tr(env^T x) over isometries x;
+ * when env has zero singular values that minimiser is not unique and
+ * mera_polar_update returns MERA_ENUMERIC.  This call first runs
+ * mera_polar_update on env; if that reports MERA_ENUMERIC it runs it again on
+ * env - t * prev with t = tie * ||env||_F / ||prev||_F (FP64 reductions and
+ * axpy on the device), which among those minimisers picks (up to O(tie)) the
+ * one closest to prev, the tensor being updated.  Full-rank environments give
+ * exactly the output of mera_polar_update.
+ * prev_d: device, rows x cols doubles, same blocking as env_d (not modified).
+ * tie: finite, > 0 (the optimiser uses 1e-10).  Workspace:
+ * mera_workspace_bytes(MERA_OP_POLAR_NEAR, rows, cols, 0, 0) (the polar
+ * workspace plus rows * cols doubles for the shifted environment).  Returns
+ * MERA_EINVAL for a null prev_d or a bad tie, MERA_ENUMERIC when the shifted
+ * environment fails too (or env or prev is zero); otherwise as
+ * mera_polar_update.  Synchronises `hip_stream`. */
+int mera_polar_update_near(const double* env_d, const double* prev_d, int64_t rows, int64_t cols,
+                           double tie, double* out_d, double* sv_d, void* ws_d, size_t ws_bytes,
+                           void* hip_stream);
+
 /* Fixed point of the scale-invariant descending superoperator by iteration
  * (Sec. II.B): power-iteration steps rho <- D_AVG(rho), rho <- (rho + rho^T)/2,
  * rho <- rho/tr(rho), with the symmetrisation and renormalisation in FP64.
@@ -218,7 +239,7 @@ int mera_tfim_hamiltonian(double field, double* h_host /* 64 doubles */, double*
 
 /* Workspace in bytes needed by `op` for the given shape, precision and
  * placement (placement is ignored where it does not matter).  For
- * MERA_OP_POLAR, din = rows and dout = cols.  Returns 0 for invalid
+ * MERA_OP_POLAR and MERA_OP_POLAR_NEAR, din = rows and dout = cols.  Returns 0 for invalid
  * arguments.  Pure host function. */
 size_t mera_workspace_bytes(int op, int32_t din, int32_t dout, int precision, int placement);
 

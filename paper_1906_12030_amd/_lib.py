@@ -18,7 +18,7 @@ MERA_LEFT, MERA_RIGHT, MERA_AVG = 0, 1, 2
 MERA_FP64, MERA_FP32, MERA_BF16X3 = 0, 1, 2
 (MERA_OP_ASCEND, MERA_OP_DESCEND, MERA_OP_ENV_U, MERA_OP_ENV_W, MERA_OP_POLAR,
  MERA_OP_FIXED_POINT, MERA_OP_ENERGY, MERA_OP_TREE_ASCEND, MERA_OP_TREE_DESCEND,
- MERA_OP_TREE_ENV_W) = range(10)
+ MERA_OP_TREE_ENV_W, MERA_OP_POLAR_NEAR) = range(11)
 
 EXPORTED = (
     "mera_ascend", "mera_descend", "mera_env_u", "mera_env_w", "mera_polar_update",
@@ -26,6 +26,7 @@ EXPORTED = (
     "mera_strerror", "mera_last_error", "mera_flops", "mera_profile_begin", "mera_profile_end",
     "mera_workspace_bytes_min", "mera_mfma_peak", "mera_contract", "mera_schedule_plan",
     "mera_descend_noalloc", "mera_tree_descend", "mera_tree_ascend", "mera_tree_env_w",
+    "mera_polar_update_near",
 )
 
 
@@ -70,6 +71,7 @@ def load() -> ctypes.CDLL:
     lib.mera_env_u.argtypes = [lp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
     lib.mera_env_w.argtypes = [lp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, sz, vp]
     lib.mera_polar_update.argtypes = [vp, i64, i64, vp, vp, vp, sz, vp]
+    lib.mera_polar_update_near.argtypes = [vp, vp, i64, i64, dbl, vp, vp, vp, sz, vp]
     lib.mera_fixed_point_rho.argtypes = [lp, vp, i32, dbl, ctypes.c_int, vp, vp, sz, vp]
     lib.mera_energy.argtypes = [vp, vp, i64, vp, vp]
     lib.mera_tfim_hamiltonian.argtypes = [dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
@@ -96,7 +98,8 @@ def load() -> ctypes.CDLL:
     lib.mera_profile_end.argtypes = [ctypes.POINTER(MeraProfileEntry), i32, ctypes.POINTER(i32)]
     lib.mera_profile_end.restype = ctypes.c_int
     for name in ("mera_ascend", "mera_descend", "mera_env_u", "mera_env_w", "mera_polar_update",
-                 "mera_fixed_point_rho", "mera_energy", "mera_tfim_hamiltonian"):
+                 "mera_polar_update_near", "mera_fixed_point_rho", "mera_energy",
+                 "mera_tfim_hamiltonian"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -146,6 +149,11 @@ def mera_env_w(layer, h_d, rho_d, env_d, placement, precision, ws_d, ws_bytes, s
 
 def mera_polar_update(env_d, rows, cols, out_d, sv_d, ws_d, ws_bytes, stream):
     return load().mera_polar_update(env_d, rows, cols, out_d, sv_d, ws_d, ws_bytes, stream)
+
+
+def mera_polar_update_near(env_d, prev_d, rows, cols, tie, out_d, sv_d, ws_d, ws_bytes, stream):
+    return load().mera_polar_update_near(env_d, prev_d, rows, cols, tie, out_d, sv_d, ws_d, ws_bytes,
+                                         stream)
 
 
 def mera_fixed_point_rho(layer, rho_d, iters, tol, precision, resid_d, ws_d, ws_bytes, stream):

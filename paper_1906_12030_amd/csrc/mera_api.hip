@@ -809,6 +809,37 @@ PolarWs polar_layout(Ctx& cx, int64_t rows, int64_t cols) {
   return p;
 }
 
+// Host-side checks shared by the polar calls; `near` adds the shifted copy of
+// env (rows * cols doubles) in front of the polar buffers.
+int check_polar(const double* env_d, int64_t rows, int64_t cols, const double* out_d, const double* sv_d,
+                const void* ws_d, size_t ws_bytes, bool near) {
+  if (!env_d || !out_d) {
+    set_err("null tensor pointer");
+    return MERA_EINVAL;
+  }
+  if (rows < 1 || cols < 1 || rows < cols || rows * cols >= (int64_t(1) << 31)) {
+    set_err("polar needs rows >= cols >= 1");
+    return MERA_ESHAPE;
+  }
+  if (sv_d && cols > mera::kSymEigMaxOrder) {
+    set_err("polar: singular values are available for cols <= " + std::to_string(mera::kSymEigMaxOrder));
+    return MERA_ESHAPE;
+  }
+  Ctx dry;
+  dry.dry = true;
+  if (near) dry.take_d(rows * cols);
+  polar_layout(dry, rows, cols);
+  if (ws_bytes < dry.off) {
+    set_err("workspace too small: need " + std::to_string(dry.off) + " bytes");
+    return MERA_EWORKSPACE;
+  }
+  if (!ws_d || reinterpret_cast<uintptr_t>(ws_d) % 256) {
+    set_err("workspace null or not 256-byte aligned");
+    return MERA_EINVAL;
+  }
+  return MERA_OK;
+}
+
 // Newton-Schulz polar iteration on the buffers of `p` (see polar_layout), then
 // out = -X and, when sv_d is given, the eigenvalues of X^T Y (the singular
 // values of Y, largest first).  Synchronises `s`.
@@ -1231,35 +1262,57 @@ int mera_energy(const double* h_d, const double* rho_d, int64_t n, double* e_d, 
 
 int mera_polar_update(const double* env_d, int64_t rows, int64_t cols, double* out_d, double* sv_d,
                       void* ws_d, size_t ws_bytes, void* hip_stream) {
-  if (!env_d || !out_d) {
-    set_err("null tensor pointer");
-    return MERA_EINVAL;
-  }
-  if (rows < 1 || cols < 1 || rows < cols || rows * cols >= (int64_t(1) << 31)) {
-    set_err("polar needs rows >= cols >= 1");
-    return MERA_ESHAPE;
-  }
-  if (sv_d && cols > mera::kSymEigMaxOrder) {
-    set_err("polar: singular values are available for cols <= " + std::to_string(mera::kSymEigMaxOrder));
-    return MERA_ESHAPE;
-  }
-  Ctx dry;
-  dry.dry = true;
-  polar_layout(dry, rows, cols);
-  if (ws_bytes < dry.off) {
-    set_err("workspace too small: need " + std::to_string(dry.off) + " bytes");
-    return MERA_EWORKSPACE;
-  }
-  if (!ws_d || reinterpret_cast<uintptr_t>(ws_d) % 256) {
-    set_err("workspace null or not 256-byte aligned");
-    return MERA_EINVAL;
-  }
+  int st = check_polar(env_d, rows, cols, out_d, sv_d, ws_d, ws_bytes, false);
+  if (st) return st;
   Ctx cx;
   cx.dry = false;
   cx.base = static_cast<char*>(ws_d);
   cx.s = static_cast<hipStream_t>(hip_stream);
   PolarWs p = polar_layout(cx, rows, cols);
   return polar_run(p, env_d, rows, cols, out_d, sv_d, cx.s);
+}
+
+int mera_polar_update_near(const double* env_d, const double* prev_d, int64_t rows, int64_t cols,
+                           double tie, double* out_d, double* sv_d, void* ws_d, size_t ws_bytes,
+                           void* hip_stream) {
+  if (!prev_d) {
+    set_err("null previous tensor");
+    return MERA_EINVAL;
+  }
+  if (!(tie > 0.0) || !std::isfinite(tie)) {
+    set_err("tie weight must be a finite number > 0");
+    return MERA_EINVAL;
+  }
+  int st = check_polar(env_d, rows, cols, out_d, sv_d, ws_d, ws_bytes, true);
+  if (st) return st;
+  Ctx cx;
+  cx.dry = false;
+  cx.base = static_cast<char*>(ws_d);
+  cx.s = static_cast<hipStream_t>(hip_stream);
+  double* shifted = cx.take_d(rows * cols);
+  PolarWs p = polar_layout(cx, rows, cols);
+  st = polar_run(p, env_d, rows, cols, out_d, sv_d, cx.s);
+  if (st != MERA_ENUMERIC) return st;
+  // rank-deficient (or zero) environment: t = tie ||env||_F / ||prev||_F, then
+  // the polar factor of env - t prev
+  const int64_t n = rows * cols;
+  double host[2];
+  hipError_t e;
+  auto fail = [&](hipError_t err, const char* what) {
+    set_err(std::string("polar near ") + what + ": " + hipGetErrorString(err));
+    return MERA_EDEVICE;
+  };
+  if ((e = mera::launch_reduce(4, env_d, nullptr, n, p.partial, p.scal, cx.s))) return fail(e, "norm");
+  if ((e = mera::launch_reduce(4, prev_d, nullptr, n, p.partial, p.scal + 1, cx.s))) return fail(e, "norm");
+  if ((e = hipMemcpyAsync(host, p.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, cx.s))) return fail(e, "copy");
+  if ((e = hipStreamSynchronize(cx.s))) return fail(e, "sync");
+  if (!(host[0] > 0.0) || !std::isfinite(host[0]) || !(host[1] > 0.0) || !std::isfinite(host[1]))
+    return MERA_ENUMERIC;  // a zero environment or previous tensor leaves nothing to break the tie with
+  const double t = tie * std::sqrt(host[0] / host[1]);
+  if ((e = hipMemcpyAsync(shifted, env_d, n * sizeof(double), hipMemcpyDeviceToDevice, cx.s)))
+    return fail(e, "copy");
+  if ((e = mera::launch_axpby(prev_d, shifted, -t, 1.0, n, cx.s))) return fail(e, "axpby");
+  return polar_run(p, shifted, rows, cols, out_d, sv_d, cx.s);
 }
 
 int mera_fixed_point_rho(const mera_layer* si, double* rho_d, int32_t iters, double tol, int precision,
@@ -1461,9 +1514,10 @@ size_t mera_workspace_bytes(int op, int32_t din, int32_t dout, int precision, in
   Ctx cx;
   if (precision < MERA_FP64 || precision > MERA_BF16X3) return 0;
   if (op == MERA_OP_ENERGY) return 0;
-  if (op == MERA_OP_POLAR) {
+  if (op == MERA_OP_POLAR || op == MERA_OP_POLAR_NEAR) {
     if (din < 1 || dout < 1 || din < dout) return 0;
     cx.dry = true;
+    if (op == MERA_OP_POLAR_NEAR) cx.take_d((int64_t)din * dout);
     polar_layout(cx, din, dout);
     return cx.off;
   }

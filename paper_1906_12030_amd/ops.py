@@ -213,18 +213,32 @@ def polar_update(env: torch.Tensor, rows: int, cols: int, out=None, check=True, 
 TIE_BREAK = 1e-10
 
 
+def polar_update_near(env: torch.Tensor, prev: torch.Tensor, rows: int, cols: int, tie=TIE_BREAK,
+                      out=None, check=True):
+    """-U V^T of env, or for a rank-deficient env that of env - t prev with
+    t = tie ||env|| / ||prev|| (mera_polar_update_near).  Returns (out, status)."""
+    env, prev = _dev(env), _dev(prev)
+    if prev.shape != env.shape or prev.device != env.device:
+        raise ValueError("prev must have the shape and device of env")
+    if out is None:
+        out = torch.empty(env.shape, dtype=torch.float64, device=env.device)
+    nb = _lib.mera_workspace_bytes(_lib.MERA_OP_POLAR_NEAR, rows, cols, 0, 0)
+    ws, wsb = WORKSPACE.get(nb, env.device)
+    st = _lib.mera_polar_update_near(env.data_ptr(), prev.data_ptr(), rows, cols, float(tie),
+                                     out.data_ptr(), None, ws, wsb, _stream(env.device))
+    if check:
+        _lib.check(st, "mera_polar_update_near")
+    return out, st
+
+
 def _update(env: torch.Tensor, rows: int, cols: int, prev, check: bool) -> torch.Tensor:
     """-U V^T of env.  When env is rank-deficient the minimiser of tr(env^T x) over isometries
-    is not unique and mera_polar_update reports MERA_ENUMERIC; with `prev` (the tensor being
-    updated) the update is then taken for env - t prev, t = TIE_BREAK ||env|| / ||prev||, which
-    selects among those minimisers (up to O(t)) the one closest to prev."""
-    out, _, st = polar_update(env, rows, cols, check=False)
-    if st == _lib.MERA_ENUMERIC and prev is not None:
-        t = TIE_BREAK * float(env.norm()) / float(prev.norm())
-        out, _, st = polar_update(env - t * prev, rows, cols, check=False)
-    if check:
-        _lib.check(st, "mera_polar_update")
-    return out
+    is not unique; with `prev` (the tensor being updated) the library then takes the update
+    of env - t prev, t = TIE_BREAK ||env|| / ||prev||, which selects among those minimisers
+    (up to O(t)) the one closest to prev."""
+    if prev is None:
+        return polar_update(env, rows, cols, check=check)[0]
+    return polar_update_near(env, prev, rows, cols, check=check)[0]
 
 
 def update_u(env: torch.Tensor, check=True, prev=None) -> torch.Tensor:

@@ -289,3 +289,21 @@ def test_every_schedule_is_planned_and_sized(lib):
                     assert 0 < least <= full, (op, prec, din, dout, pl, least, full)
                     n += 1
     assert n > 500
+
+
+def test_polar_update_near_argument_checks(lib):
+    fake = 4096
+    plain = _lib.mera_workspace_bytes(_lib.MERA_OP_POLAR, 16, 4, 0, 0)
+    need = _lib.mera_workspace_bytes(_lib.MERA_OP_POLAR_NEAR, 16, 4, 0, 0)
+    assert need == plain + 16 * 4 * 8  # the shifted environment (512 bytes, already aligned)
+    assert _lib.mera_workspace_bytes(_lib.MERA_OP_POLAR_NEAR, 4, 16, 0, 0) == 0
+    f = _lib.mera_polar_update_near
+    assert f(fake, None, 16, 4, 1e-10, fake, None, fake, need, None) == _lib.MERA_EINVAL
+    assert f(fake, fake, 16, 4, 0.0, fake, None, fake, need, None) == _lib.MERA_EINVAL
+    assert f(fake, fake, 16, 4, float("nan"), fake, None, fake, need, None) == _lib.MERA_EINVAL
+    assert f(fake, fake, 4, 16, 1e-10, fake, None, fake, need, None) == _lib.MERA_ESHAPE
+    assert f(fake, fake, 16, 4, 1e-10, fake, None, fake, need - 1, None) == _lib.MERA_EWORKSPACE
+    assert f(fake, fake, 16, 4, 1e-10, fake, None, fake + 8, need, None) == _lib.MERA_EINVAL
+    assert f(None, fake, 16, 4, 1e-10, fake, None, fake, need, None) == _lib.MERA_EINVAL
+    st, _ = _lib.mera_schedule_plan(_lib.MERA_OP_POLAR_NEAR, 16, 4, 0, _lib.MERA_AVG)
+    assert st == _lib.MERA_EINVAL

@@ -176,6 +176,39 @@ def test_rank_deficient_update_takes_the_minimiser_closest_to_the_previous_tenso
     assert np.abs(x - expected).max() < 2e-5
 
 
+def test_polar_update_near_is_the_plain_update_for_a_full_rank_environment(ops):
+    """mera_polar_update_near on a full-rank environment (u and w blockings): bitwise the
+    output of mera_polar_update; the previous tensor does not enter."""
+    rng = np.random.default_rng(12)
+    for rows, cols in ((16, 16), (64, 8)):
+        env = gpu(rng.standard_normal((rows, cols)))
+        prev = gpu(_polar_np(rng.standard_normal((rows, cols))))
+        plain = host(ops.polar_update(env, rows, cols)[0])
+        near, st = ops.polar_update_near(env, prev, rows, cols)
+        assert st == 0
+        assert np.array_equal(host(near), plain)
+
+
+def test_polar_update_near_matches_the_shifted_environment_update(ops):
+    """For a rank-deficient environment the call returns the plain update of
+    env - t prev, t = tie ||env||_F / ||prev||_F (the shift formed here with numpy)."""
+    rng = np.random.default_rng(13)
+    rows, cols, r = 36, 6, 3
+    env = rng.standard_normal((rows, r)) @ rng.standard_normal((r, cols))
+    prev = _polar_np(rng.standard_normal((rows, cols)))
+    tie = 1e-8
+    near, st = ops.polar_update_near(gpu(env), gpu(prev), rows, cols, tie=tie)
+    assert st == 0
+    t = tie * np.linalg.norm(env) / np.linalg.norm(prev)
+    ref = host(ops.polar_update(gpu(env - t * prev), rows, cols)[0])
+    assert np.abs(host(near) - ref).max() < 1e-10
+    x = host(near)
+    assert np.abs(x.T @ x - np.eye(cols)).max() < 1e-12
+    # a zero environment has no tie to break
+    _, st0 = ops.polar_update_near(gpu(np.zeros((rows, cols))), gpu(prev), rows, cols, check=False)
+    assert st0 == 5  # MERA_ENUMERIC
+
+
 @pytest.mark.parametrize("d", [2, 3, 4])
 def test_fixed_point(ops, d):
     rng = np.random.default_rng(40 + d)
