@@ -12,11 +12,13 @@
 //     than 256 x 192); twice the tile edge of the 128 x 128 kernel halves the
 //     bytes that have to come through L2 per flop;
 //   * the order of fragment reads, loads and MFMAs after each k-tile's barrier
-//     is fixed with scheduling groups: streamed fragments are read in pairs of
-//     blocks, right after the wait for the previous pair, so that each wait
-//     has 23 MFMAs of cover (the LDS-DMA loads in the loop make the compiler
-//     wait for all outstanding LDS reads at every wait, so the reads must be
-//     issued early rather than counted);
+//     is fixed with scheduling groups: only the fragments of A blocks 0, 1 and
+//     B blocks 0, 1 are read before the first MFMA (all eight waves read
+//     them at once after the barrier), the other fragments are read in groups
+//     right after a wait, each with 11 or 23 MFMAs of cover before the next
+//     wait (the LDS-DMA loads in the loop make the compiler wait for all
+//     outstanding LDS reads at every wait, so the reads must be issued early
+//     rather than counted);
 //   * operand k-tiles (32 split elements, 128 bytes, per row) go straight
 //     from global memory into LDS with global_load_lds_dwordx4, in a two-stage ring
 //     with one barrier per k-tile: the loads of tile kt+1 fly while the
@@ -50,6 +52,8 @@ namespace b3x {
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
 
 constexpr int kThreadsX = 512;
 constexpr int kBM = 256;
@@ -189,13 +193,16 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[Geo<BN
   }
   if (p.cgroup8 && p.splits == 1 && alpha == 1.0 && beta == 0.0 && m0 + kBM <= (uint32_t)p.M &&
       n0 + BN <= (uint32_t)p.N) {
-    // Whole tile inside C, plain split store along n: lane l of a wave writes the
-    // 16-byte hi (l even) or lo (l odd) half of one 8-column group of a tile row, so
-    // one store instruction of a wave covers 64 consecutive group halves of C.
+    // Whole tile inside C, plain split store along n.  The two lanes of a pair
+    // (2g, 2g+1) share one 8-column group of a tile row: each converts four of
+    // its values (the first or the last four) to hi and lo bf16 halves, the
+    // pair swaps the halves the other lane stores (DPP), and lane 2g writes the
+    // group's 16-byte hi half, lane 2g+1 its lo half, so one store
+    // instruction of a wave covers 64 consecutive group halves of C.
     constexpr int HALVES = BN / 4;       // group halves per tile row
     constexpr int ROWS8 = 16 / G::kWGN;  // rows of each 16-row group written by a wave
     constexpr int IT8 = ROWS8 * HALVES / 64;
-    static_assert(ROWS8 * HALVES % 64 == 0, "epilogue geometry");
+    static_assert(ROWS8 * HALVES % 64 == 0 && HALVES % 2 == 0, "epilogue geometry");
     const int wr8 = (wave % G::kWGN) * ROWS8;
     const bool lo = (lane & 1) != 0;
     __syncthreads();  // offsets staged
@@ -203,11 +210,21 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[Geo<BN
     int64_t cb[IT8];
 #pragma unroll
     for (int it = 0; it < IT8; ++it) {
-      const int idx = it * 64 + lane;
+      const int idx = it * 64 + lane;  // a pair never straddles a tile row (HALVES is even)
       rr[it] = wr8 + idx / HALVES;
       cc[it] = 8 * ((idx % HALVES) >> 1);
       cb[it] = cols[cc[it]];
     }
+    // two bf16 (round to nearest even) packed in a word, and the value of each half
+    auto pack = [](float a, float b) {
+      return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2_t{a, b}, bf2_t));
+    };
+    auto low_of = [](uint32_t w) { return __uint_as_float(w << 16); };
+    auto high_of = [](uint32_t w) { return __uint_as_float(w & 0xffff0000u); };
+    // the value of lane l ^ 1 (quad_perm 1, 0, 3, 2)
+    auto swap_pair = [](uint32_t v) {
+      return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);
+    };
     char* __restrict__ Cb = static_cast<char*>(p.c);
 #pragma unroll
     for (int i = 0; i < G::kWMB; ++i) {
@@ -220,22 +237,14 @@ __device__ __forceinline__ void write_tile_x(const TcArgs& p, f4_t (&acc)[Geo<BN
       __syncthreads();
 #pragma unroll
       for (int it = 0; it < IT8; ++it) {
-        const float* s8 = st + rr[it] * LD + cc[it];
-        const f4_t x0 = *reinterpret_cast<const f4_t*>(s8);
-        const f4_t x1 = *reinterpret_cast<const f4_t*>(s8 + 4);
+        const f4_t x = *reinterpret_cast<const f4_t*>(st + rr[it] * LD + cc[it] + (lo ? 4 : 0));
         const int64_t ro = rows[wm + i * 16 + rr[it]];
-        u4_t w;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float a = e < 2 ? x0[2 * e] : x1[2 * e - 4];
-          const float b = e < 2 ? x0[2 * e + 1] : x1[2 * e - 3];
-          uint32_t ha = bf16_bits(a), hb = bf16_bits(b);
-          if (lo) {
-            ha = bf16_bits(a - bf16_value((uint16_t)ha));
-            hb = bf16_bits(b - bf16_value((uint16_t)hb));
-          }
-          w[e] = ha | (hb << 16);
-        }
+        const uint32_t h0 = pack(x[0], x[1]), h1 = pack(x[2], x[3]);
+        const uint32_t l0 = pack(x[0] - low_of(h0), x[1] - high_of(h0));
+        const uint32_t l1 = pack(x[2] - low_of(h1), x[3] - high_of(h1));
+        // lane 2g sends its lo words and keeps its hi words; lane 2g+1 the reverse
+        const uint32_t r0 = swap_pair(lo ? h0 : l0), r1 = swap_pair(lo ? h1 : l1);
+        const u4_t w = lo ? u4_t{r0, r1, l0, l1} : u4_t{h0, h1, r0, r1};
         // the group starts at element ro + cb (a multiple of 8): byte 4 (ro + cb)
         *reinterpret_cast<u4_t*>(Cb + 4 * (ro + cb[it]) + (lo ? 16 : 0)) = w;
       }
@@ -367,9 +376,11 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
   // barrier, and the last tile reloads its own (in-bounds) k range into the
   // free stage, so everything after the barrier is branch-free; the order of
   // the fragment reads, the loads and the MFMAs there is fixed by scheduling
-  // groups: the held fragments and the first two streamed blocks, the loads
-  // of tile kt+1, then pairs of streamed blocks, each pair's first MFMA
-  // followed by the reads of the next pair (pin_pairs).
+  // groups: the fragments of A blocks 0, 1 and B blocks 0, 1, the loads of
+  // tile kt+1, their MFMAs (the reads of the remaining held fragments and of
+  // the next two streamed blocks after the first of them), then pairs of
+  // streamed blocks, each pair's first MFMA followed by the reads of the next
+  // pair (pin_pairs).
   issue(0, 4 * kw.oa, 4 * kw.ob);
   for (int kt = 0; kt < nk; ++kt) {
     if (kt + 1 < nk) kw.next();
@@ -384,73 +395,94 @@ __global__ __launch_bounds__(kThreadsX) void tc_b3x_kernel(TcArgs p) {
       r[0] = *reinterpret_cast<const u4_t*>(base + row16 * 16 * kRowBytes + x0);
       r[1] = *reinterpret_cast<const u4_t*>(base + row16 * 16 * kRowBytes + x1);
     };
+    // MFMAs of A blocks [i0, i1) x B blocks [j0, j1), the three products in
+    // turn (consecutive MFMAs into one accumulator are (i1 - i0)(j1 - j0)
+    // apart); a and b map a block to its fragment slots
+    auto mfmas = [&](int i0, int i1, int j0, int j1, auto&& a, auto&& b) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int i = i0; i < i1; ++i)
+#pragma unroll
+          for (int j = j0; j < j1; ++j) {
+            const u4_t(&fa)[2] = a(i);
+            const u4_t(&fb)[2] = b(j);
+            // products lo x hi, hi x lo, hi x hi
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf8_t, fa[q == 0 ? 1 : 0]), __builtin_bit_cast(bf8_t, fb[q == 1 ? 1 : 0]),
+                acc[i][j], 0, 0, 0);
+          }
+    };
     if constexpr (G::kWMB == 8) {
       // 2 x 4 (or 2 x 3) waves: B fragments held for the k-tile, A fragments
-      // streamed through a ring of four, read two blocks ahead
-      u4_t ra[4][2], rb[G::kWNB][2];
-#pragma unroll
-      for (int j = 0; j < G::kWNB; ++j) rd(sb + bbase, j, rb[j]);
+      // streamed through a ring of four.  First A blocks 0, 1 against B blocks
+      // 0, 1 (8 fragment reads before the first MFMA), then against the other
+      // B blocks, then pairs of A blocks against all of them.
+      constexpr int NB = G::kWNB;
+      u4_t ra[4][2], rb[NB][2];
+      auto fa = [&](int i) -> const u4_t(&)[2] { return ra[i % 4]; };
+      auto fb = [&](int j) -> const u4_t(&)[2] { return rb[j]; };
       rd(sa + abase, 0, ra[0]);
       rd(sa + abase, 1, ra[1]);
-      issue((kt + 1) & 1, ka, kb);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        if (i % 2 == 0 && i + 2 < 8) {
-          rd(sa + abase, i + 2, ra[(i + 2) % 4]);
-          rd(sa + abase, i + 3, ra[(i + 3) % 4]);
-        }
-        const bf8_t ah = __builtin_bit_cast(bf8_t, ra[i % 4][0]);
-        const bf8_t al = __builtin_bit_cast(bf8_t, ra[i % 4][1]);
-#pragma unroll
-        for (int j = 0; j < G::kWNB; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, __builtin_bit_cast(bf8_t, rb[j][0]),
-                                                            acc[i][j], 0, 0, 0);
-#pragma unroll
-        for (int j = 0; j < G::kWNB; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf8_t, rb[j][1]),
-                                                            acc[i][j], 0, 0, 0);
-#pragma unroll
-        for (int j = 0; j < G::kWNB; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf8_t, rb[j][0]),
-                                                            acc[i][j], 0, 0, 0);
-      }
-      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 2 * G::kWNB + 4, 0);
-      __builtin_amdgcn_sched_group_barrier(kSgVmem, G::kAIns + G::kBIns, 0);
-      pin_pairs<0, 8, 3 * G::kWNB>();
-    } else {
-      // 4 x 2 waves: A fragments held for the k-tile, B fragments streamed
-      // through a ring of four, read two blocks ahead
-      constexpr int NB = G::kWNB;
-      u4_t ra[G::kWMB][2], rb[4][2];
-#pragma unroll
-      for (int i = 0; i < G::kWMB; ++i) rd(sa + abase, i, ra[i]);
       rd(sb + bbase, 0, rb[0]);
       rd(sb + bbase, 1, rb[1]);
       issue((kt + 1) & 1, ka, kb);
+      mfmas(0, 2, 0, 2, fa, fb);
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j % 2 == 0) {
-          if (j + 2 < NB) rd(sb + bbase, j + 2, rb[(j + 2) % 4]);
-          if (j + 3 < NB) rd(sb + bbase, j + 3, rb[(j + 3) % 4]);
+      for (int j = 2; j < NB; ++j) rd(sb + bbase, j, rb[j]);
+      rd(sa + abase, 2, ra[2]);
+      rd(sa + abase, 3, ra[3]);
+      mfmas(0, 2, 2, NB, fa, fb);
+#pragma unroll
+      for (int i = 2; i < 8; i += 2) {
+        if (i + 2 < 8) {
+          rd(sa + abase, i + 2, ra[(i + 2) % 4]);
+          rd(sa + abase, i + 3, ra[(i + 3) % 4]);
         }
-        const bf8_t bh = __builtin_bit_cast(bf8_t, rb[j % 4][0]);
-        const bf8_t bl = __builtin_bit_cast(bf8_t, rb[j % 4][1]);
-#pragma unroll
-        for (int i = 0; i < G::kWMB; ++i)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, ra[i][1]), bh,
-                                                            acc[i][j], 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < G::kWMB; ++i)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, ra[i][0]), bl,
-                                                            acc[i][j], 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < G::kWMB; ++i)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, ra[i][0]), bh,
-                                                            acc[i][j], 0, 0, 0);
+        mfmas(i, i + 2, 0, NB, fa, fb);
       }
-      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 2 * G::kWMB + 4, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 8, 0);
       __builtin_amdgcn_sched_group_barrier(kSgVmem, G::kAIns + G::kBIns, 0);
-      pin_pairs<0, NB, 3 * G::kWMB>();
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 2 * (NB - 2) + 4, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 11, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 6 * (NB - 2), 0);
+      pin_pairs<2, 8, 3 * NB>();
+    } else {
+      // 4 x 2 waves: A fragments held for the k-tile, B fragments streamed
+      // through a ring of four.  First A blocks 0, 1 against B blocks 0, 1
+      // (8 fragment reads before the first MFMA), then A blocks 2, 3 against
+      // them, then all A blocks against pairs of B blocks.
+      constexpr int NB = G::kWNB;
+      constexpr int MB = G::kWMB;
+      static_assert(MB == 4, "4 x 2 wave grid");
+      u4_t ra[MB][2], rb[4][2];
+      auto fa = [&](int i) -> const u4_t(&)[2] { return ra[i]; };
+      auto fb = [&](int j) -> const u4_t(&)[2] { return rb[j % 4]; };
+      rd(sa + abase, 0, ra[0]);
+      rd(sa + abase, 1, ra[1]);
+      rd(sb + bbase, 0, rb[0]);
+      rd(sb + bbase, 1, rb[1]);
+      issue((kt + 1) & 1, ka, kb);
+      mfmas(0, 2, 0, 2, fa, fb);
+      rd(sa + abase, 2, ra[2]);
+      rd(sa + abase, 3, ra[3]);
+      rd(sb + bbase, 2, rb[2]);
+      rd(sb + bbase, 3, rb[3]);
+      mfmas(2, 4, 0, 2, fa, fb);
+#pragma unroll
+      for (int j = 2; j < NB; j += 2) {
+        if (j + 2 < NB) rd(sb + bbase, j + 2, rb[(j + 2) % 4]);
+        if (j + 3 < NB) rd(sb + bbase, j + 3, rb[(j + 3) % 4]);
+        mfmas(0, MB, j, j + 2 < NB ? j + 2 : NB, fa, fb);
+      }
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 8, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgVmem, G::kAIns + G::kBIns, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 8, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 11, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 12, 0);
+      pin_pairs<2, NB, 3 * MB>();
     }
   }
   wait_vmcnt<0>();    // the last tile's reload has landed
