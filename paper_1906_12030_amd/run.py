@@ -175,7 +175,8 @@ def main(argv=None):
         d, lam, calls = scaling.scaling_dimensions(m.si[0], m.si[1], k=a.dims)
         print(json.dumps({"scaling_dimensions": [round(float(x), 6) for x in d], "matvecs": calls}), flush=True)
     if a.compare_precisions:
-        compare_precisions(m, h1, shift, a.compare_precisions.split(","), a.iters, a.dims, a.compare_sweeps)
+        compare_precisions(m, h1, shift, a.compare_precisions.split(","), a.iters, a.dims, a.compare_sweeps,
+                           a.si_levels)
     return e
 
 
@@ -209,19 +210,19 @@ def _copy(m):
                          m.rho_star.clone())
 
 
-def compare_precisions(m, h1, shift, precisions, iters, dims, nsweeps=0):
+def compare_precisions(m, h1, shift, precisions, iters, dims, nsweeps=0, si_levels=1):
     """Energy, rho* and scaling dimensions of the same tensors in several contraction
     precisions; differences against the first one listed.  With nsweeps > 0, also the
-    optimisation outcome: nsweeps sweeps from the same state in each precision, the
-    resulting tensors evaluated in FP64 (rho* by iters warm-started FP64 iterations,
-    FP64 descent and trace)."""
+    optimisation outcome: nsweeps sweeps (si_levels scale-invariant environment levels)
+    from the same state in each precision, the resulting tensors evaluated in FP64 (rho* by
+    iters warm-started FP64 iterations, FP64 descent and trace)."""
     if nsweeps > 0:
         eref = None
         for prec in precisions:
             mm = _copy(m)
             fp, _, ep = prec.partition("/")  # "bf16x3/fp64": fixed point in bf16x3, environments in FP64
             for _ in range(nsweeps):
-                sweep.sweep(mm, h1, shift, iters, fp, env_precision=ep or None)
+                sweep.sweep(mm, h1, shift, iters, fp, si_levels, env_precision=ep or None)
             sweep.initial_fixed_point(mm, iters, "fp64")
             e = sweep.energy(mm, h1, shift)
             rec = {"precision": prec, "sweeps_from_state": nsweeps, "energy_fp64_eval": e}
