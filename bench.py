@@ -333,7 +333,7 @@ def evaluation_vs_oracle(args, h1, shift, sweep, prec):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the sharded multi-GPU path is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
